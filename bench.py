@@ -1,0 +1,212 @@
+"""Benchmark of the Rydberg state-vector hot path on one MI355X.
+
+Workload: the 27-atom random register (30x30 um box, 5 um minimum distance, seed 0) under
+the adiabatic sweep (0.5 us ramps around a 3 us plateau, Omega_max and delta_max drawn from
+U[2pi, 2pi*3] rad/us), dt = 10 ns, tolerance 1e-10 (complex128) / 1e-7 (complex64).
+
+A step is one time step of eq. (6): the Lanczos Krylov exponential (H psi passes, FP64
+reductions, host tridiagonal exponential) and the Krylov combination.  W untimed steps run
+first (steps 0..W-1 from |0...0>), then K steps are timed (steps W..W+K-1).  Reported:
+  value      simulated microseconds per wall second of the complex128 path (whole job, state
+             resident in HBM),
+  roofline   H psi (the dominant operation) at the step-300 parameters: algorithmic bytes
+             (40 B/amplitude c128) / average duration from HIP events on the launch stream,
+  c64        the same for complex64 storage with FP64 Lanczos scalars, plus its infidelity
+             against the complex128 result of the same steps,
+  cpu_baseline  the CPU oracle's H psi at the same size, scaled to sim-us/s.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "H*psi HBM GB/s + sim-us/sec at N=27; served solves/s, p50/p99 at fidelity 1e-6"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def hpsi_time(rsv, reg, pulses, step, dt_ns, n, prec, reps=30, warm=5):
+    import torch
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    g = torch.Generator(device="cuda:0").manual_seed(42)
+    x = torch.randn(1 << n, dtype=dt, device="cuda:0", generator=g)
+    x /= torch.linalg.vector_norm(x)
+    y = torch.empty_like(x)
+    for _ in range(warm):
+        rsv.rsv_apply_hamiltonian(reg, pulses, step, dt_ns, x, y)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        rsv.rsv_apply_hamiltonian(reg, pulses, step, dt_ns, x, y)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return ms
+
+
+def evolve_timed(rsv, ctx, w, prec, warmup, steps):
+    import torch
+    reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, prec)
+    pulses = rsv.PulseArrays(w.omega, w.delta)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    psi = torch.zeros(1 << w.n_atoms, dtype=dt, device="cuda:0")
+    psi[0] = 1
+    tol = w.tol if prec == "c128" else 1e-7
+    st_w = rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, tol, w.kmax, 12, 0, warmup), psi)
+    log(f"{prec}: warmup {warmup} steps in {st_w.seconds:.2f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, tol, w.kmax, 12, warmup, steps), psi)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"{prec}: {steps} steps in {wall:.3f} s, {st.krylov_iters} Krylov iterations")
+    return reg, psi, st, wall
+
+
+def pmc_traffic(prec):
+    """HBM bytes per H psi application from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"hpsi_random27_{prec}_traffic.json")
+    src = os.path.join(ROOT, "paper_2510_09813_amd", "csrc", "hpsi.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("hpsi_src_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec.get("bytes_per_application")
+
+
+def cpu_baseline(w, iters_per_step, budget_s=25.0):
+    """The oracle's H psi at N=27 (one application, tensor-slicing form) on the host cores,
+    scaled to simulated us per wall second with the GPU run's Krylov iterations per step."""
+    from oracle import model
+    from threadpoolctl import threadpool_info
+    n = w.n_atoms
+    rng = np.random.default_rng(42)
+    psi = (rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)).astype(np.complex128)
+    u = model.interaction_matrix(w.xyz, w.c6)
+    pars = model.step_parameters(n, w.omega, w.delta, None, w.dt_ns, 300)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        model.apply_hamiltonian(psi, u, *pars)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s / 2 or reps >= 3:
+            break
+    t_apply = (time.perf_counter() - t0) / reps
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    step_s = t_apply * iters_per_step
+    return {
+        "value": round(w.dt_ns * 1e-3 / step_s, 8), "unit": "sim-us/s",
+        "cores": int(threads), "kind": "oracle",
+        "sample": (f"{reps} oracle H|psi> application(s) at N={n} (complex128, step-300 "
+                   f"parameters), {t_apply:.2f} s each = {40 * (1 << n) / t_apply / 1e9:.2f} GB/s "
+                   f"algorithmic; scaled by the GPU run's {iters_per_step:.2f} H|psi> per step "
+                   f"(the oracle's re-orthogonalisation and combination not counted)"),
+        "hpsi_seconds": t_apply,
+        "host_cpus": len(os.sched_getaffinity(0)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the state vector of one job lives on one MI355X; "
+              "see the design notes for how the path would shard across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_09813_amd import rsv
+    from paper_2510_09813_amd import workloads as wl
+    torch.cuda.set_device(0)
+    w = wl.random27()
+    n = w.n_atoms
+    K, W = args.steps, args.warmup
+    if W + K > w.n_steps:
+        raise SystemExit(f"warmup + steps must be <= {w.n_steps}")
+    ctx = rsv.rsv_ctx_create(0)
+
+    t0 = time.perf_counter()
+    reg128, psi128, st128, wall128 = evolve_timed(rsv, ctx, w, "c128", W, K)
+    sim_us = K * w.dt_ns * 1e-3
+    iters_per_step = st128.krylov_iters / K
+
+    pulses = rsv.PulseArrays(w.omega, w.delta)
+    ms128 = hpsi_time(rsv, reg128, pulses, 300, w.dt_ns, n, "c128")
+    gbs128 = 40.0 * (1 << n) / (ms128 * 1e-3) / 1e9
+    log(f"c128 H|psi>: {ms128:.3f} ms = {gbs128:.0f} GB/s algorithmic")
+    occ = rsv.rsv_occupations_device(ctx, n, psi128, "c128")
+    shots = rsv.rsv_sample_device(ctx, n, psi128, 0, 1000, "c128")
+    out = {
+        "metric": METRIC, "value": round(sim_us / wall128, 4), "unit": "sim-us/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(wall128 / K * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "random27-sweep", "n_atoms": n, "amplitudes": 1 << n,
+                   "dt_ns": w.dt_ns, "tol": w.tol, "kmax": w.kmax,
+                   "timed_steps": f"{W}..{W + K - 1} of {w.n_steps}", "precision": "complex128"},
+        "krylov_iters_per_step": round(iters_per_step, 3),
+        "krylov_max": int(st128.krylov_max),
+        "hpsi_ms": round(ms128, 4), "hpsi_gbps": round(gbs128, 1),
+        "roofline": {"bound": "hbm", "achieved": round(gbs128, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(gbs128 / PEAK_HBM_GBS, 4),
+                     "kernel": "H|psi> at N=27 complex128 (high passes + low pass)",
+                     "traffic": pmc_traffic("c128")},
+        "occupations_sum": round(float(occ.sum()), 6), "n_shots": len(shots),
+    }
+    rsv.rsv_register_destroy(reg128)
+
+    if not args.no_c64:
+        reg64, psi64, st64, wall64 = evolve_timed(rsv, ctx, w, "c64", W, K)
+        ms64 = hpsi_time(rsv, reg64, pulses, 300, w.dt_ns, n, "c64")
+        a = psi128.cpu().numpy()
+        b = psi64.cpu().numpy().astype(np.complex128)
+        a /= np.linalg.norm(a)
+        b /= np.linalg.norm(b)
+        r = b - np.vdot(a, b) * a
+        infid = float(np.vdot(r, r).real)
+        occ64 = rsv.rsv_occupations_device(ctx, n, psi64, "c64")
+        out["c64"] = {
+            "sim_us_per_s": round(sim_us / wall64, 4), "ms_per_step": round(wall64 / K * 1e3, 3),
+            "hpsi_ms": round(ms64, 4), "hpsi_gbps": round(20.0 * (1 << n) / (ms64 * 1e-3) / 1e9, 1),
+            "hpsi_frac": round(20.0 * (1 << n) / (ms64 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "infidelity_vs_c128": infid, "max_occ_err_vs_c128": float(np.abs(occ64 - occ).max()),
+            "krylov_iters_per_step": round(st64.krylov_iters / K, 3),
+            "traffic": pmc_traffic("c64"),
+        }
+        rsv.rsv_register_destroy(reg64)
+        del psi64
+    del psi128
+    torch.cuda.empty_cache()
+    rsv.rsv_ctx_destroy(ctx)
+
+    if not args.no_cpu:
+        log("cpu baseline: oracle H|psi> at N=27 ...")
+        out["cpu_baseline"] = cpu_baseline(w, iters_per_step)
+    log(f"total {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

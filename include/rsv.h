@@ -1,0 +1,170 @@
+/* librsv -- Rydberg state-vector emulation on AMD Instinct MI355X (gfx950).
+ *
+ * Computes the emu-sv method of "Efficient Emulation of Neutral Atom Quantum Hardware"
+ * (arXiv 2510.09813): time evolution psi(t_{k+1}) = exp(-i H_k dt) psi(t_k) (eq. 6) of the
+ * Rydberg Hamiltonian (eq. 3, Sec. II.A)
+ *
+ *   H(t) = sum_i Omega_i/2 (cos phi_i sigma^x_i - sin phi_i sigma^y_i) - sum_i delta_i n_i
+ *          + sum_{i>j} C / |r_i - r_j|^6 n_i n_j
+ *
+ * on a 2^N state vector.  The pulse is piecewise constant with midpoint sampling
+ * (Sec. III): step k uses the mean of the 1 ns samples at floor(m) and ceil(m),
+ * m = (k + 1/2) dt.  exp(-i H_k dt) psi is the Lanczos Krylov exponential of Sec. III.A,
+ * grown until its a-posteriori error estimate is below the tolerance.  H psi is
+ * matrix-free: the diagonal (interaction energies built once per register, detuning added
+ * from the bit pattern) plus one level swap per atom scaled by the drive (Sec. III.A).
+ *
+ * Conventions
+ *  - |1> is the Rydberg level, n = |1><1|; the default initial state is |0...0> (Sec. II.B).
+ *  - Amplitude index b: atom i (0-based) is bit N-1-i, i.e. atom 0 is the most significant
+ *    bit (row-major c_{i1...iN}, Sec. II.B).  Bitstring character i is atom i.
+ *  - sigma^y = [[0,-i],[i,0]] in (|0>,|1>): <1|h_i|0> = Omega_i/2 e^{-i phi_i}.
+ *  - Units: hbar = 1, positions in um, time in us (dt and samples on a 1 ns grid), Omega and
+ *    delta in rad/us, phi in rad, C in rad us^-1 um^6.
+ *  - State vectors are interleaved (re, im): complex128 (RSV_C128) or complex64 (RSV_C64).
+ *    In RSV_C64 the state, the Krylov basis and H psi are complex64 while every inner
+ *    product, norm and Lanczos coefficient is FP64 and the tridiagonal exponential is host
+ *    FP64.
+ *
+ * Ownership and errors
+ *  - Host input arrays are read during the call only (copied where kept).
+ *  - Handles belong to the library until the matching *_destroy.
+ *  - Device pointers passed to *_device calls and rsv_apply_hamiltonian stay owned by the
+ *    caller, must hold 2^N amplitudes of the register's precision and must not overlap.
+ *  - Every call returns RSV_OK or an error code; nothing throws across this boundary.
+ *    rsv_last_error() returns a thread-local description of the last failure.
+ *  - A context is used by one host thread at a time.  Work is issued on the given HIP stream
+ *    (NULL = the default stream); calls return after the work finished unless stated.
+ */
+#ifndef RSV_H_
+#define RSV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RSV_OK = 0,
+  RSV_EINVAL = 1,      /* invalid argument: sizes, grid, non-finite values, coincident atoms */
+  RSV_ENOMEM = 2,      /* the context's HBM budget or the device cannot hold the workspace */
+  RSV_EDEVICE = 3,     /* a HIP runtime call failed */
+  RSV_ENOTCONV = 4,    /* Krylov exponential not converged within kmax even after sub-steps */
+  RSV_ENUMERIC = 5,    /* a Lanczos coefficient or norm became NaN or Inf */
+  RSV_EBUSY = 6,       /* resource in use (server queue full) */
+  RSV_ECANCELLED = 7   /* the job was cancelled */
+};
+
+typedef enum { RSV_C128 = 0, RSV_C64 = 1 } rsv_precision;
+
+typedef struct rsv_ctx rsv_ctx;
+typedef struct rsv_register rsv_register;
+typedef struct rsv_result rsv_result;
+typedef struct rsv_server rsv_server;
+
+/* Pulses sampled on the 1 ns grid t_n = n ns, n = 0..n_samples-1 (Sec. III).
+ * per_site = 0: each array has n_samples values shared by all atoms;
+ * per_site = 1: arrays are [n_atoms][n_samples], row-major.  phi may be NULL (zero). */
+typedef struct {
+  int64_t n_samples;
+  int per_site;
+  const double* omega; /* rad/us */
+  const double* delta; /* rad/us */
+  const double* phi;   /* rad */
+} rsv_pulses;
+
+/* dt_ns:      step in ns (integer multiple of the sampling grid, Sec. III); the pulse must
+ *             cover a whole number of steps: (n_samples - 1) % dt_ns == 0.
+ * tol:        Krylov tolerance on the a-posteriori estimate beta_m |[exp(-i dt T_m) e_1]_m|
+ *             times |psi| (the "precision" of Sec. III.A), > 0.
+ * kmax:       maximum Krylov dimension, 2..64.  Without convergence the step is split into
+ *             sub-steps with the same H_k (exact), at most max_substep_depth halvings deep.
+ * first_step, n_steps: evolve steps [first_step, first_step + n_steps); n_steps < 0 means up
+ *             to the end of the pulse.  Stepping is Markov, so (k, psi_k) is a checkpoint. */
+typedef struct {
+  int dt_ns;
+  double tol;
+  int kmax;
+  int max_substep_depth;
+  int64_t first_step;
+  int64_t n_steps;
+} rsv_evolve_opts;
+
+typedef struct {
+  int64_t steps;          /* time steps taken */
+  int64_t krylov_iters;   /* Lanczos iterations (H psi applications), summed */
+  int64_t krylov_max;     /* largest Krylov dimension used */
+  int64_t substeps;       /* extra sub-steps taken after non-convergence */
+  double norm_final;      /* |psi| after the last step (1 up to rounding) */
+  double seconds;         /* wall time of the evolution, entry to final synchronisation */
+  double bytes_hpsi;      /* algorithmic HBM bytes of the H psi passes */
+} rsv_stats;
+
+/* ------------------------------------------------------------------ context */
+const char* rsv_version(void);
+const char* rsv_last_error(void);
+/* hbm_budget_bytes = 0: no budget beyond the device's free memory. */
+int rsv_ctx_create(int hip_device, size_t hbm_budget_bytes, rsv_ctx** out);
+void rsv_ctx_destroy(rsv_ctx* ctx);
+/* Bytes of device memory currently held by the context's registers and results. */
+size_t rsv_ctx_bytes_in_use(const rsv_ctx* ctx);
+
+/* ------------------------------------------------------------------ register
+ * Builds U_ij = C/|r_i - r_j|^6 on the host (eq. 3) and the interaction diagonal
+ * E_b = sum_{i>j} U_ij n_i n_j on the device (2^N values, FP64 for RSV_C128, FP32 for
+ * RSV_C64), once per register (Sec. III.A keeps only the diagonal of H).
+ * n_atoms in 1..30; xyz_um is [n_atoms][3]; coincident atoms give RSV_EINVAL. */
+int rsv_register_create(rsv_ctx* ctx, int n_atoms, const double* xyz_um, double c6,
+                        rsv_precision prec, rsv_register** out);
+void rsv_register_destroy(rsv_register* reg);
+/* Copies E into a caller device buffer of 2^N reals of the register's precision. */
+int rsv_register_diagonal(rsv_register* reg, void* d_out, void* hip_stream);
+
+/* Device bytes rsv_evolve needs for a register of n_atoms: (kmax + 3) vectors (Krylov basis
+ * of kmax + 1, the Lanczos residual, the high-bit H psi partial) plus the diagonal, the state
+ * and the reduction buffers -- the admission formula of the server. */
+size_t rsv_workspace_bytes(int n_atoms, int kmax, rsv_precision prec);
+
+/* ------------------------------------------------------------------ hot path
+ * One H_k psi: d_out = H_k d_in with the parameters of step `step` for the given dt
+ * (Sec. III.A).  d_in, d_out: caller device buffers of 2^N amplitudes. */
+int rsv_apply_hamiltonian(rsv_register* reg, const rsv_pulses* pulses, int64_t step, int dt_ns,
+                          const void* d_in, void* d_out, void* hip_stream);
+
+/* Evolves the caller's device state in place through the requested steps (eq. 6). */
+int rsv_evolve_device(rsv_register* reg, const rsv_pulses* pulses, const rsv_evolve_opts* opts,
+                      void* d_psi_inout, void* hip_stream, rsv_stats* stats_out);
+
+/* Host-level form: psi0_host is 2^N complex128 values (NULL = |0...0>); the result keeps
+ * the evolved state on the device until rsv_result_destroy. */
+int rsv_evolve(rsv_register* reg, const rsv_pulses* pulses, const rsv_evolve_opts* opts,
+               const void* psi0_host, rsv_result** out);
+int rsv_result_state(const rsv_result* res, void* psi_host_c128);
+/* <n_i> for i = 0..N-1 (FP64 accumulation, normalised by |psi|^2). */
+int rsv_result_occupations(const rsv_result* res, double* n_out);
+/* n_shots basis indices drawn from |psi_b|^2 / |psi|^2 in shot order.  Shot s uses the s-th
+ * output x_s of SplitMix64 seeded with `seed`, u_s = (x_s >> 11) 2^-53, and returns the
+ * smallest b with CDF(b) > u_s CDF(2^N - 1) (the largest b of nonzero mass if rounding
+ * leaves none). */
+int rsv_result_sample(const rsv_result* res, uint64_t seed, int n_shots, uint64_t* idx_out);
+int rsv_result_stats(const rsv_result* res, rsv_stats* out);
+void rsv_result_destroy(rsv_result* res);
+
+/* The same outputs for a caller device state of n_atoms in precision prec. */
+int rsv_occupations_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
+                           double* n_out, void* hip_stream);
+int rsv_sample_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
+                      uint64_t seed, int n_shots, uint64_t* idx_out, void* hip_stream);
+
+/* Host FP64 tridiagonal exponential used by every Lanczos step (Sec. III.A):
+ * y = exp(-i tau T) e_1 for T = tridiag(beta, alpha, beta), m in 1..64.  Host only. */
+int rsv_tridiag_expm(int m, const double* alpha, const double* beta, double tau, double* y_re,
+                     double* y_im);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSV_H_ */

@@ -86,12 +86,14 @@ def _samples_len(x):
 
 
 def evolve(xyz, c6, omega, delta, phi, t_ns: int, dt_ns: int, psi0=None, method="lanczos",
-           tol: float = 1e-13, kmax: int = 60, steps=None, return_stats=False):
+           tol: float = 1e-13, kmax: int = 60, steps=None, first_step: int = 0,
+           return_stats=False):
     """Evolve psi0 (default |0...0>) through steps 0..K-1 of eq. (6), K = t_ns / dt_ns.
 
     method = "dense" uses exp by eigendecomposition of each H_k (re-used while the
     midpoint parameters do not change); "lanczos" uses the Krylov exponential with full
-    re-orthogonalisation.  ``steps`` limits the run to the first ``steps`` steps."""
+    re-orthogonalisation.  The run covers steps first_step .. first_step + steps - 1 (all
+    remaining steps when ``steps`` is None), starting from psi0 at step first_step."""
     n = int(np.asarray(xyz).shape[0])
     _check_grid(_samples_len(omega), t_ns, dt_ns)
     u = model.interaction_matrix(xyz, c6)
@@ -100,11 +102,12 @@ def evolve(xyz, c6, omega, delta, phi, t_ns: int, dt_ns: int, psi0=None, method=
         psi[0] = 1.0
     else:
         psi[:] = np.asarray(psi0, dtype=np.complex128)
-    n_steps = t_ns // dt_ns if steps is None else min(steps, t_ns // dt_ns)
+    total = t_ns // dt_ns
+    n_steps = total - first_step if steps is None else min(steps, total - first_step)
     tau = dt_ns * 1e-3
     stats = {"iters": 0, "substeps": 0, "steps": n_steps}
     cache_key, cache = None, None
-    for k in range(n_steps):
+    for k in range(first_step, first_step + n_steps):
         om, de, ph = model.step_parameters(n, omega, delta, phi, dt_ns, k)
         if method == "dense":
             key = (om.tobytes(), de.tobytes(), ph.tobytes())
@@ -122,7 +125,7 @@ def evolve(xyz, c6, omega, delta, phi, t_ns: int, dt_ns: int, psi0=None, method=
     return (psi, stats) if return_stats else psi
 
 
-def evolve_workload(w, method="lanczos", psi0=None, steps=None, **kw):
+def evolve_workload(w, method="lanczos", psi0=None, steps=None, first_step=0, **kw):
     """Convenience wrapper taking a ``workloads.Workload``-like object."""
     return evolve(w.xyz, w.c6, w.omega, w.delta, w.phi, w.t_ns, w.dt_ns, psi0=psi0,
-                  method=method, steps=steps, **kw)
+                  method=method, steps=steps, first_step=first_step, **kw)

@@ -1,0 +1,183 @@
+// Streaming vector kernels of the Lanczos recurrence (Sec. III.A) and the Krylov
+// combination psi_{k+1} = |psi_k| V_m exp(-i dt T_m) e_1 (eq. 6).
+//
+// All are HBM-bound single sweeps.  Every reduction is two-stage and deterministic: each
+// workgroup writes one FP64 partial in a fixed grid-stride order, then one workgroup sums
+// the partials in a fixed order (no floating-point atomics), so a result does not depend on
+// what else runs on the device.
+#include "common.cuh"
+
+namespace rsv {
+namespace {
+
+constexpr int kPerThread = 8;
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void lanczos_update_kernel(
+    const Cx<R>* __restrict__ w, const Cx<R>* __restrict__ v, const double sv,
+    const double* __restrict__ d_alpha, Cx<R>* __restrict__ u, double* __restrict__ partial,
+    const size_t count) {
+  __shared__ double red[4];
+  const double a = d_alpha[0] * sv;
+  double acc = 0.0;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+    const Cx<R> wi = w[i], vi = v[i];
+    Cx<R> r;
+    r.x = (R)((double)wi.x - a * (double)vi.x);
+    r.y = (R)((double)wi.y - a * (double)vi.y);
+    u[i] = r;
+    acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+  }
+  const double t = block_sum_256(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void combine_kernel(const CombineCoef c,
+                                                         Cx<R>* __restrict__ out,
+                                                         double* __restrict__ partial,
+                                                         const size_t count) {
+  __shared__ double red[4];
+  __shared__ const Cx<R>* ptr[kMaxKrylov];
+  if (threadIdx.x < c.m) ptr[threadIdx.x] = (const Cx<R>*)c.x[threadIdx.x];
+  __syncthreads();
+  double acc = 0.0;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+    double re = 0.0, im = 0.0;
+    for (int l = 0; l < c.m; ++l) {
+      const Cx<R> xi = ptr[l][i];
+      re += c.re[l] * (double)xi.x - c.im[l] * (double)xi.y;
+      im += c.re[l] * (double)xi.y + c.im[l] * (double)xi.x;
+    }
+    Cx<R> r;
+    r.x = (R)re;
+    r.y = (R)im;
+    out[i] = r;
+    acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+  }
+  const double t = block_sum_256(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void norm2_kernel(const Cx<R>* __restrict__ x,
+                                                       double* __restrict__ partial,
+                                                       const size_t count) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+    const Cx<R> xi = x[i];
+    acc += (double)xi.x * (double)xi.x + (double)xi.y * (double)xi.y;
+  }
+  const double t = block_sum_256(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// One workgroup of 256 threads: thread t sums a contiguous slice in order, then a fixed tree.
+__global__ __launch_bounds__(kBlock) void finalize_kernel(const double* __restrict__ partial,
+                                                          const int64_t count,
+                                                          double* __restrict__ dst) {
+  __shared__ double red[4];
+  const int64_t per = (count + kBlock - 1) / kBlock;
+  const int64_t lo = (int64_t)threadIdx.x * per;
+  const int64_t hi = lo + per < count ? lo + per : count;
+  double acc = 0.0;
+  for (int64_t i = lo; i < hi; ++i) acc += partial[i];
+  const double t = block_sum_256(acc, red);
+  if (threadIdx.x == 0) dst[0] = t;
+}
+
+template <class RS, class RD>
+__global__ __launch_bounds__(kBlock) void convert_kernel(const Cx<RS>* __restrict__ src,
+                                                         Cx<RD>* __restrict__ dst,
+                                                         const size_t count) {
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+    const Cx<RS> v = src[i];
+    Cx<RD> r;
+    r.x = (RD)v.x;
+    r.y = (RD)v.y;
+    dst[i] = r;
+  }
+}
+
+}  // namespace
+
+int64_t vec_num_partials(int prec, int n) {
+  (void)prec;
+  return stream_grid(size_t(1) << n, kPerThread);
+}
+
+hipError_t lanczos_update(int prec, int n, const void* w, const void* v, double sv,
+                          const double* d_alpha, void* u, double* partial, hipStream_t s) {
+  const size_t count = size_t(1) << n;
+  const uint32_t g = stream_grid(count, kPerThread);
+  if (prec == kC128)
+    hipLaunchKernelGGL(lanczos_update_kernel<double>, dim3(g), dim3(kBlock), 0, s,
+                       (const double2*)w, (const double2*)v, sv, d_alpha, (double2*)u, partial,
+                       count);
+  else
+    hipLaunchKernelGGL(lanczos_update_kernel<float>, dim3(g), dim3(kBlock), 0, s,
+                       (const float2*)w, (const float2*)v, sv, d_alpha, (float2*)u, partial,
+                       count);
+  return hipGetLastError();
+}
+
+hipError_t krylov_combine(int prec, int n, const CombineCoef& c, void* out, double* partial,
+                          hipStream_t s) {
+  const size_t count = size_t(1) << n;
+  const uint32_t g = stream_grid(count, kPerThread);
+  if (prec == kC128)
+    hipLaunchKernelGGL(combine_kernel<double>, dim3(g), dim3(kBlock), 0, s, c, (double2*)out,
+                       partial, count);
+  else
+    hipLaunchKernelGGL(combine_kernel<float>, dim3(g), dim3(kBlock), 0, s, c, (float2*)out,
+                       partial, count);
+  return hipGetLastError();
+}
+
+hipError_t norm2_partial(int prec, int n, const void* x, double* partial, hipStream_t s) {
+  const size_t count = size_t(1) << n;
+  const uint32_t g = stream_grid(count, kPerThread);
+  if (prec == kC128)
+    hipLaunchKernelGGL(norm2_kernel<double>, dim3(g), dim3(kBlock), 0, s, (const double2*)x,
+                       partial, count);
+  else
+    hipLaunchKernelGGL(norm2_kernel<float>, dim3(g), dim3(kBlock), 0, s, (const float2*)x,
+                       partial, count);
+  return hipGetLastError();
+}
+
+hipError_t finalize_sum(const double* partial, int64_t count, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, s, partial, count, dst);
+  return hipGetLastError();
+}
+
+hipError_t convert_from_c128(int prec, int n, const void* src, void* dst, hipStream_t s) {
+  const size_t count = size_t(1) << n;
+  const uint32_t g = stream_grid(count, kPerThread);
+  if (prec == kC128)
+    hipLaunchKernelGGL((convert_kernel<double, double>), dim3(g), dim3(kBlock), 0, s,
+                       (const double2*)src, (double2*)dst, count);
+  else
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(kBlock), 0, s,
+                       (const double2*)src, (float2*)dst, count);
+  return hipGetLastError();
+}
+
+hipError_t convert_to_c128(int prec, int n, const void* src, void* dst, hipStream_t s) {
+  const size_t count = size_t(1) << n;
+  const uint32_t g = stream_grid(count, kPerThread);
+  if (prec == kC128)
+    hipLaunchKernelGGL((convert_kernel<double, double>), dim3(g), dim3(kBlock), 0, s,
+                       (const double2*)src, (double2*)dst, count);
+  else
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(kBlock), 0, s,
+                       (const float2*)src, (double2*)dst, count);
+  return hipGetLastError();
+}
+
+}  // namespace rsv

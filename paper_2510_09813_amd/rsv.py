@@ -1,0 +1,274 @@
+"""ctypes binding of librsv (include/rsv.h): argument marshalling only.
+
+Every function has the name of the C call it wraps; status codes other than RSV_OK raise
+``RsvError`` with the library's message.  Device buffers are torch tensors (complex128 for
+RSV_C128, complex64 for RSV_C64) or raw device addresses; torch only provides memory and
+streams, all arithmetic runs in librsv's HIP kernels.  There is no fallback: if librsv.so is
+missing or cannot be loaded, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsv.so")
+
+RSV_OK, RSV_EINVAL, RSV_ENOMEM, RSV_EDEVICE, RSV_ENOTCONV, RSV_ENUMERIC, RSV_EBUSY, \
+    RSV_ECANCELLED = range(8)
+RSV_C128, RSV_C64 = 0, 1
+PRECISIONS = {"c128": RSV_C128, "c64": RSV_C64}
+
+# Every symbol include/rsv.h declares; the CPU test suite checks that the library exports them.
+EXPORTED = [
+    "rsv_version", "rsv_last_error", "rsv_ctx_create", "rsv_ctx_destroy", "rsv_ctx_bytes_in_use",
+    "rsv_register_create", "rsv_register_destroy", "rsv_register_diagonal", "rsv_workspace_bytes",
+    "rsv_apply_hamiltonian", "rsv_evolve_device", "rsv_evolve", "rsv_result_state",
+    "rsv_result_occupations", "rsv_result_sample", "rsv_result_stats", "rsv_result_destroy",
+    "rsv_occupations_device", "rsv_sample_device", "rsv_tridiag_expm",
+]
+
+
+class RsvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librsv error {code}: {msg}")
+        self.code = code
+
+
+class Pulses(C.Structure):
+    _fields_ = [("n_samples", C.c_int64), ("per_site", C.c_int),
+                ("omega", C.POINTER(C.c_double)), ("delta", C.POINTER(C.c_double)),
+                ("phi", C.POINTER(C.c_double))]
+
+
+class EvolveOpts(C.Structure):
+    _fields_ = [("dt_ns", C.c_int), ("tol", C.c_double), ("kmax", C.c_int),
+                ("max_substep_depth", C.c_int), ("first_step", C.c_int64),
+                ("n_steps", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("krylov_iters", C.c_int64), ("krylov_max", C.c_int64),
+                ("substeps", C.c_int64), ("norm_final", C.c_double), ("seconds", C.c_double),
+                ("bytes_hpsi", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Loads librsv.so (torch first, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401
+    except Exception:  # pragma: no cover - torch is optional for host-only calls
+        pass
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u64, dbl, sz = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
+    pd = C.POINTER(C.c_double)
+    sig = {
+        "rsv_version": (C.c_char_p, []),
+        "rsv_last_error": (C.c_char_p, []),
+        "rsv_ctx_create": (i32, [i32, sz, C.POINTER(vp)]),
+        "rsv_ctx_destroy": (None, [vp]),
+        "rsv_ctx_bytes_in_use": (sz, [vp]),
+        "rsv_register_create": (i32, [vp, i32, pd, dbl, i32, C.POINTER(vp)]),
+        "rsv_register_destroy": (None, [vp]),
+        "rsv_register_diagonal": (i32, [vp, vp, vp]),
+        "rsv_workspace_bytes": (sz, [i32, i32, i32]),
+        "rsv_apply_hamiltonian": (i32, [vp, C.POINTER(Pulses), i64, i32, vp, vp, vp]),
+        "rsv_evolve_device": (i32, [vp, C.POINTER(Pulses), C.POINTER(EvolveOpts), vp, vp,
+                                    C.POINTER(Stats)]),
+        "rsv_evolve": (i32, [vp, C.POINTER(Pulses), C.POINTER(EvolveOpts), vp, C.POINTER(vp)]),
+        "rsv_result_state": (i32, [vp, vp]),
+        "rsv_result_occupations": (i32, [vp, pd]),
+        "rsv_result_sample": (i32, [vp, u64, i32, C.POINTER(C.c_uint64)]),
+        "rsv_result_stats": (i32, [vp, C.POINTER(Stats)]),
+        "rsv_result_destroy": (None, [vp]),
+        "rsv_occupations_device": (i32, [vp, i32, i32, vp, pd, vp]),
+        "rsv_sample_device": (i32, [vp, i32, i32, vp, u64, i32, C.POINTER(C.c_uint64), vp]),
+        "rsv_tridiag_expm": (i32, [i32, pd, pd, dbl, pd, pd]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != RSV_OK:
+        raise RsvError(rc, lib().rsv_last_error().decode())
+
+
+def _dptr(buf) -> int:
+    """Device address of a torch tensor (must be contiguous) or an int address."""
+    if isinstance(buf, int):
+        return buf
+    if not buf.is_contiguous():
+        raise ValueError("device buffer must be contiguous")
+    return int(buf.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return int(torch.cuda.current_stream().cuda_stream) or None
+        except Exception:  # pragma: no cover
+            pass
+        return None
+    return int(stream)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class PulseArrays:
+    """Keeps the sample arrays alive while librsv reads them."""
+
+    def __init__(self, omega, delta, phi=None):
+        self.omega, self.delta = _f64(omega), _f64(delta)
+        self.phi = None if phi is None else _f64(phi)
+        if self.omega.shape != self.delta.shape or (self.phi is not None and self.phi.shape != self.omega.shape):
+            raise ValueError("omega, delta and phi must have the same shape")
+        pd = C.POINTER(C.c_double)
+        self.struct = Pulses(self.omega.shape[-1], 1 if self.omega.ndim == 2 else 0,
+                             self.omega.ctypes.data_as(pd), self.delta.ctypes.data_as(pd),
+                             self.phi.ctypes.data_as(pd) if self.phi is not None else None)
+
+
+def evolve_opts(dt_ns: int, tol: float = 1e-10, kmax: int = 30, max_substep_depth: int = 12,
+                first_step: int = 0, n_steps: int = -1) -> EvolveOpts:
+    return EvolveOpts(dt_ns, tol, kmax, max_substep_depth, first_step, n_steps)
+
+
+# ------------------------------------------------------------------------- C calls
+def rsv_version() -> str:
+    return lib().rsv_version().decode()
+
+
+def rsv_ctx_create(device: int = 0, budget: int = 0):
+    h = C.c_void_p()
+    _check(lib().rsv_ctx_create(device, budget, C.byref(h)))
+    return h
+
+
+def rsv_ctx_destroy(ctx):
+    lib().rsv_ctx_destroy(ctx)
+
+
+def rsv_ctx_bytes_in_use(ctx) -> int:
+    return int(lib().rsv_ctx_bytes_in_use(ctx))
+
+
+def rsv_register_create(ctx, xyz, c6: float, precision="c128"):
+    xyz = _f64(xyz).reshape(-1, 3)
+    h = C.c_void_p()
+    prec = PRECISIONS.get(precision, precision)
+    _check(lib().rsv_register_create(ctx, xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)),
+                                     float(c6), prec, C.byref(h)))
+    return h
+
+
+def rsv_register_destroy(reg):
+    lib().rsv_register_destroy(reg)
+
+
+def rsv_register_diagonal(reg, d_out, stream=None):
+    _check(lib().rsv_register_diagonal(reg, _dptr(d_out), _stream(stream)))
+
+
+def rsv_workspace_bytes(n_atoms: int, kmax: int, precision="c128") -> int:
+    return int(lib().rsv_workspace_bytes(n_atoms, kmax, PRECISIONS.get(precision, precision)))
+
+
+def rsv_apply_hamiltonian(reg, pulses: PulseArrays, step: int, dt_ns: int, d_in, d_out, stream=None):
+    _check(lib().rsv_apply_hamiltonian(reg, C.byref(pulses.struct), step, dt_ns, _dptr(d_in),
+                                       _dptr(d_out), _stream(stream)))
+
+
+def rsv_evolve_device(reg, pulses: PulseArrays, opts: EvolveOpts, d_psi, stream=None) -> Stats:
+    st = Stats()
+    _check(lib().rsv_evolve_device(reg, C.byref(pulses.struct), C.byref(opts), _dptr(d_psi),
+                                   _stream(stream), C.byref(st)))
+    return st
+
+
+def rsv_evolve(reg, pulses: PulseArrays, opts: EvolveOpts, psi0=None):
+    h = C.c_void_p()
+    buf = None
+    if psi0 is not None:
+        buf = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+    _check(lib().rsv_evolve(reg, C.byref(pulses.struct), C.byref(opts),
+                            buf.ctypes.data if buf is not None else None, C.byref(h)))
+    return h
+
+
+def rsv_result_state(res, n_atoms: int) -> np.ndarray:
+    out = np.empty(1 << n_atoms, dtype=np.complex128)
+    _check(lib().rsv_result_state(res, out.ctypes.data))
+    return out
+
+
+def rsv_result_occupations(res, n_atoms: int) -> np.ndarray:
+    out = np.empty(n_atoms, dtype=np.float64)
+    _check(lib().rsv_result_occupations(res, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def rsv_result_sample(res, seed: int, n_shots: int) -> np.ndarray:
+    out = np.empty(n_shots, dtype=np.uint64)
+    _check(lib().rsv_result_sample(res, seed, n_shots, out.ctypes.data_as(C.POINTER(C.c_uint64))))
+    return out
+
+
+def rsv_result_stats(res) -> Stats:
+    st = Stats()
+    _check(lib().rsv_result_stats(res, C.byref(st)))
+    return st
+
+
+def rsv_result_destroy(res):
+    lib().rsv_result_destroy(res)
+
+
+def rsv_occupations_device(ctx, n_atoms: int, d_psi, precision="c128", stream=None) -> np.ndarray:
+    out = np.empty(n_atoms, dtype=np.float64)
+    _check(lib().rsv_occupations_device(ctx, n_atoms, PRECISIONS.get(precision, precision),
+                                        _dptr(d_psi), out.ctypes.data_as(C.POINTER(C.c_double)),
+                                        _stream(stream)))
+    return out
+
+
+def rsv_sample_device(ctx, n_atoms: int, d_psi, seed: int, n_shots: int, precision="c128",
+                      stream=None) -> np.ndarray:
+    out = np.empty(n_shots, dtype=np.uint64)
+    _check(lib().rsv_sample_device(ctx, n_atoms, PRECISIONS.get(precision, precision),
+                                   _dptr(d_psi), seed, n_shots,
+                                   out.ctypes.data_as(C.POINTER(C.c_uint64)), _stream(stream)))
+    return out
+
+
+def rsv_tridiag_expm(alpha, beta, tau: float):
+    a, b = _f64(alpha), _f64(beta)
+    m = a.size
+    if b.size != max(m - 1, 0):
+        raise ValueError("beta must have m - 1 entries")
+    yr, yi = np.empty(m), np.empty(m)
+    pd = C.POINTER(C.c_double)
+    _check(lib().rsv_tridiag_expm(m, a.ctypes.data_as(pd), b.ctypes.data_as(pd) if m > 1 else None,
+                                  float(tau), yr.ctypes.data_as(pd), yi.ctypes.data_as(pd)))
+    return yr + 1j * yi
