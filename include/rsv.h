@@ -158,6 +158,67 @@ int rsv_occupations_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const 
 int rsv_sample_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
                       uint64_t seed, int n_shots, uint64_t* idx_out, void* hip_stream);
 
+/* ------------------------------------------------------------------ serving
+ * A server evolves a stream of independent jobs (each a register, its pulses and options)
+ * on one device with continuous batching: n_lanes jobs run at once, each on its own HIP
+ * stream, so their kernels overlap on the device; a queued job is admitted as soon as a
+ * lane is free and its device footprint (rsv_server_job_bytes: the Krylov workspace of
+ * kmax + 3 vectors, the diagonal, the state and output scratch) fits in the server's
+ * arena, first fit in arrival order.  The arena is allocated once at creation, so serving
+ * never allocates or frees device memory.  A job's result does not depend on what else
+ * runs: every reduction has a fixed order. */
+typedef struct {
+  int n_lanes;        /* concurrent jobs, 1..16 */
+  size_t arena_bytes; /* device memory reserved for jobs; 0 = three quarters of free memory */
+  int max_queue;      /* queued jobs beyond this make rsv_server_submit return RSV_EBUSY; 0 = no limit */
+} rsv_server_opts;
+
+typedef struct {
+  int n_atoms;
+  const double* xyz_um; /* [n_atoms][3] */
+  double c6;
+  rsv_precision prec;
+  rsv_pulses pulses;
+  rsv_evolve_opts opts;
+  const void* psi0_host; /* 2^N complex128 values, NULL = |0...0> */
+  int n_shots;           /* bitstring samples to draw from the final state (seeded by seed) */
+  uint64_t seed;
+  int return_state;      /* 1: the completion carries the final state as complex128 */
+  uint64_t tag;          /* caller's label, returned unchanged */
+} rsv_job_desc;
+
+typedef struct {
+  uint64_t job_id, tag;
+  int status; /* RSV_OK, or the error the job ended with (RSV_ECANCELLED when cancelled) */
+  int n_atoms, n_shots;
+  double t_submit, t_start, t_end; /* seconds since rsv_server_create */
+  rsv_stats stats;
+  double* occupations; /* [n_atoms]; these arrays stay valid until rsv_server_release */
+  uint64_t* samples;   /* [n_shots] or NULL */
+  void* state;         /* [2^N] complex128 or NULL */
+  char error[160];
+} rsv_completion;
+
+int rsv_server_create(rsv_ctx* ctx, const rsv_server_opts* opts, rsv_server** out);
+/* Device bytes one job occupies in the arena. */
+size_t rsv_server_job_bytes(int n_atoms, int kmax, rsv_precision prec, int n_shots);
+/* Copies the job (all arrays) and queues it.  RSV_ENOMEM if it can never fit the arena,
+ * RSV_EBUSY if the queue is full, RSV_EINVAL for invalid input. */
+int rsv_server_submit(rsv_server* srv, const rsv_job_desc* job, uint64_t* job_id);
+/* Waits up to timeout_ms (< 0: forever) for at least one completion and moves up to max of
+ * them to out[0..*n_out). */
+int rsv_server_poll(rsv_server* srv, rsv_completion* out, int max, int* n_out, int timeout_ms);
+/* Frees the arrays of a polled completion. */
+void rsv_server_release(rsv_server* srv, rsv_completion* c);
+/* Cancels a queued job (it completes with RSV_ECANCELLED); RSV_EBUSY if it already runs,
+ * RSV_EINVAL if unknown or finished. */
+int rsv_server_cancel(rsv_server* srv, uint64_t job_id);
+/* Jobs queued, running and completed-but-not-polled; arena bytes in use. */
+int rsv_server_status(rsv_server* srv, int* queued, int* running, int* done, size_t* arena_used);
+/* Cancels queued jobs, waits for the running ones and frees everything; completions not
+ * polled are discarded. */
+void rsv_server_destroy(rsv_server* srv);
+
 /* Host FP64 tridiagonal exponential used by every Lanczos step (Sec. III.A):
  * y = exp(-i tau T) e_1 for T = tridiag(beta, alpha, beta), m in 1..64.  Host only. */
 int rsv_tridiag_expm(int m, const double* alpha, const double* beta, double tau, double* y_re,

@@ -1,18 +1,29 @@
-// Matrix-free H|psi> for the Rydberg Hamiltonian (eq. 3 with the drive phase).
+// Matrix-free H|psi> for the Rydberg Hamiltonian (eq. 3 with the drive phase), fused with
+// the Lanczos recurrence.
 //
 // Sec. III.A applies H in two steps: the diagonal, then for every atom the amplitudes with
 // that atom's level swapped, scaled by the drive.  On gfx950 this is a bandwidth-bound
 // stencil on the n-dimensional hypercube, done in passes over LDS tiles:
 //
 //  * low pass:  a tile of 2^L contiguous amplitudes (L = 12 for complex128, 13 for
-//    complex64, 64 KiB of LDS) covers the L least significant bits.  Each thread keeps 2^(L-8)
-//    amplitudes in registers: flips of those bits never touch LDS; flips of the 8 thread-index
-//    bits read the tile.  This pass also applies the diagonal E_b read from HBM plus the
-//    detuning term, computed from the bit pattern, and the fused Lanczos terms
-//    (-c * prev, and Re<x, out> partial sums in FP64).
-//  * high passes (n > L): a tile of 2^r contiguous amplitudes (r = 2 or 3, one 64-byte run)
-//    times 2^(L-r) combinations of up to L-r high bits; flips of those high bits.  The first
-//    high pass writes t, later ones accumulate; the low pass adds t.
+//    complex64: 64 KiB of LDS, 1024 threads) covers the L least significant bits.  The
+//    thread-index bits are flipped through the LDS tile, the remaining bits inside each
+//    thread's registers.  This pass applies the diagonal E_b (read from HBM) plus the
+//    detuning computed from the bit pattern, and adds the high-pass result t.
+//  * high passes (n > L): a tile of 2^r contiguous amplitudes (a run of 64 or 128 bytes)
+//    times the combinations of up to H - r high bits flips those high bits.  The first
+//    high pass writes t, later ones accumulate into it.  A last pass with few bits left
+//    widens its contiguous run instead.
+//
+// The first pass of a sweep may *form* its input from up to three stored vectors,
+//   u = a0 x0 + (a1 + c * dot[0]) x1 + a2 x2,
+// which is the three-term Lanczos recurrence u_{k+1} = H v_k - alpha_k v_k - beta_{k-1}
+// v_{k-1} with H v_k, v_k and v_{k-1} stored unnormalised; alpha_k arrives through dot[0]
+// (device memory), so no host round trip sits between two sweeps.  That pass stores u and
+// the FP64 partial sums of |u|^2; the low pass returns the partial sums of Re<u, H u>.
+//
+// Coefficient modes (template CM): kCoefUniform (every atom shares Omega, delta, phi),
+// kCoefReal (shared and phi = 0: one real coupling, the cheapest form) and kCoefSite.
 //
 // No MFMA: the operator has no dense contraction.
 #include "common.cuh"
@@ -20,14 +31,87 @@
 namespace rsv {
 namespace {
 
+// Tile geometry per storage precision: low-pass tile bits L and threads NL; high-pass tile
+// bits H, contiguous run bits RL (RLW for a narrow last pass) and threads NH.
 template <class R> struct Geo;
-template <> struct Geo<double> { static constexpr int L = 12, H = 12, RL = 2; };
-template <> struct Geo<float> { static constexpr int L = 13, H = 13, RL = 3; };
+template <> struct Geo<double> {
+  static constexpr int L = 12, NL = 1024, H = 12, RL = 3, RLW = 6, NH = 1024;
+};
+template <> struct Geo<float> {
+  static constexpr int L = 13, NL = 1024, H = 12, RL = 3, RLW = 6, NH = 1024;
+};
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+
+// Sum of a double over an NT-thread workgroup (fixed tree; valid in thread 0).
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double* red /* NT / 64 doubles */) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) r += red[w];
+  }
+  __syncthreads();
+  return r;
+}
+
+// Device-side arguments of one pass.
+template <class R>
+struct PassArgs {
+  const Cx<R>* x0;
+  const Cx<R>* x1;
+  const Cx<R>* x2;
+  double a0, a1, a2;
+  const double* dot;  // optional: a1 += dot_coef * dot[0]
+  double dot_coef;
+  Cx<R>* u_out;       // optional: store the formed input
+  double* part_norm;  // optional: per-workgroup |u|^2
+  // high pass
+  Cx<R>* tb;
+  int accumulate, a, f0, f1;
+  // low pass
+  const R* diag;
+  Cx<R>* out;
+  double* part_dot;  // optional: per-workgroup Re<u, out>
+  uint32_t nblk;
+};
+
+template <class R>
+__device__ __forceinline__ double input_coef1(const PassArgs<R>& p) {
+  return p.dot ? p.a1 + p.dot_coef * p.dot[0] : p.a1;
+}
+
+// u = a0 x0[i] + b1 x1[i] + a2 x2[i] in FP64, rounded once to the storage precision.
+template <class R>
+__device__ __forceinline__ Cx<R> form(const PassArgs<R>& p, double b1, size_t i) {
+  const Cx<R> v0 = p.x0[i];
+  if (!p.x1 && !p.x2 && p.a0 == 1.0) return v0;
+  double re = p.a0 * (double)v0.x, im = p.a0 * (double)v0.y;
+  if (p.x1) {
+    const Cx<R> v1 = p.x1[i];
+    re += b1 * (double)v1.x;
+    im += b1 * (double)v1.y;
+  }
+  if (p.x2) {
+    const Cx<R> v2 = p.x2[i];
+    re += p.a2 * (double)v2.x;
+    im += p.a2 * (double)v2.y;
+  }
+  Cx<R> r;
+  r.x = (R)re;
+  r.y = (R)im;
+  return r;
+}
 
 // Detuning lookup: lut[256 q + v] = -sum_j delta[8q + j] over the set bits j of byte v.
 template <class R>
 __device__ __forceinline__ void build_delta_lut(const StepCoef& c, R* lut) {
-  for (int i = threadIdx.x; i < 4 * 256; i += kBlock) {
+  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
     const int q = i >> 8, v = i & 255;
     double s = 0.0;
     for (int j = 0; j < 8; ++j) {
@@ -38,9 +122,9 @@ __device__ __forceinline__ void build_delta_lut(const StepCoef& c, R* lut) {
   }
 }
 
-template <class R, bool SITE>
+template <class R, int CM>
 __device__ __forceinline__ R detuning(const StepCoef& c, const R* lut, uint32_t b) {
-  if (SITE) {
+  if (CM == kCoefSite) {
     return (lut[b & 255u] + lut[256 + ((b >> 8) & 255u)]) +
            (lut[512 + ((b >> 16) & 255u)] + lut[768 + ((b >> 24) & 255u)]);
   } else {
@@ -48,7 +132,7 @@ __device__ __forceinline__ R detuning(const StepCoef& c, const R* lut, uint32_t 
   }
 }
 
-// acc += coef(bit) * v, coefficients of bit position p.
+// acc += coef(bit) * v with the coefficients of bit position p.
 template <class R>
 __device__ __forceinline__ void cmad(Cx<R>& acc, const StepCoef& c, int p, bool bit, Cx<R> v) {
   const R cr = (R)(bit ? c.up_re[p] : c.dn_re[p]);
@@ -58,237 +142,306 @@ __device__ __forceinline__ void cmad(Cx<R>& acc, const StepCoef& c, int p, bool 
 }
 
 template <class R>
-__device__ __forceinline__ void cadd(Cx<R>& a, Cx<R> v) { a.x += v.x; a.y += v.y; }
+__device__ __forceinline__ void cadd(Cx<R>& a, Cx<R> v) {
+  a.x += v.x;
+  a.y += v.y;
+}
+
+
+// Accumulates the drive terms of one output amplitude flip by flip.
+template <class R, int CM>
+struct DriveSum {
+  Cx<R> acc = {0, 0}, all = {0, 0}, one = {0, 0};
+  __device__ __forceinline__ void add(const StepCoef& c, int p, bool bit, Cx<R> nb) {
+    if (CM == kCoefSite) {
+      cmad<R>(acc, c, p, bit, nb);
+    } else {
+      cadd<R>(all, nb);
+      if (CM == kCoefUniform && bit) cadd<R>(one, nb);
+    }
+  }
+  __device__ __forceinline__ void finish(const StepCoef& c, Cx<R>& out) {
+    if (CM == kCoefSite) {
+      cadd<R>(out, acc);
+    } else if (CM == kCoefReal) {
+      const R cr = (R)c.up_re[0];
+      out.x += cr * all.x;
+      out.y += cr * all.y;
+    } else {
+      const Cx<R> zero = {all.x - one.x, all.y - one.y};
+      cmad<R>(out, c, 0, true, one);
+      cmad<R>(out, c, 0, false, zero);
+    }
+  }
+};
 
 // ----------------------------------------------------------------------------- low pass
-template <class R, int LB, bool SITE>
-__global__ __launch_bounds__(kBlock) void hpsi_lo_kernel(
-    const StepCoef c, const R* __restrict__ diag, const Cx<R>* __restrict__ x, const double sx,
-    Cx<R>* __restrict__ out, const Cx<R>* __restrict__ tb, const Cx<R>* __restrict__ prev,
-    const double cprev, double* __restrict__ partial, const uint32_t nblk) {
+template <class R, int LB, int NT, int CM>
+__global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const PassArgs<R> p) {
   using C = Cx<R>;
-  static_assert(LB >= 8, "low pass needs at least 256 amplitudes per tile");
-  constexpr int A = 1 << (LB - 8);  // amplitudes per thread
-  constexpr int RB = LB - 8;        // bits held in registers
+  constexpr int TB = ilog2(NT);      // thread-index bits
+  static_assert(LB >= TB, "tile smaller than the workgroup");
+  constexpr int A = 1 << (LB - TB);  // amplitudes per thread
+  constexpr int RB = LB - TB;        // bits held in registers
   __shared__ C tile[1 << LB];
-  __shared__ R lut[SITE ? 1024 : 1];
-  __shared__ double red[4];
+  __shared__ R lut[CM == kCoefSite ? 1024 : 1];
+  __shared__ double red[NT / 64];
 
   const uint32_t tid = threadIdx.x;
-  const uint32_t blk = xcd_remap(blockIdx.x, nblk);
+  const uint32_t blk = xcd_remap(blockIdx.x, p.nblk);
   const uint32_t base = blk << LB;
-  if (SITE) build_delta_lut<R>(c, lut);
+  if (CM == kCoefSite) build_delta_lut<R>(c, lut);
 
-  const R s_in = (R)sx;
+  const double b1 = input_coef1(p);
   C v[A];
+  double nrm = 0.0;
 #pragma unroll
   for (int s = 0; s < A; ++s) {
-    const uint32_t e = tid + kBlock * s;
-    C a = x[base + e];
-    a.x *= s_in;
-    a.y *= s_in;
-    v[s] = a;
-    tile[e] = a;
+    const uint32_t e = tid + NT * s;
+    v[s] = form<R>(p, b1, base + e);
+    tile[e] = v[s];
+  }
+  if (p.u_out) {
+#pragma unroll
+    for (int s = 0; s < A; ++s) {
+      p.u_out[base + tid + NT * s] = v[s];
+      nrm = norm_add(nrm, (double)v[s].x, (double)v[s].y);
+    }
   }
   __syncthreads();
 
-  const R cp = (R)cprev;
   double dot = 0.0;
 #pragma unroll
   for (int s = 0; s < A; ++s) {
-    const uint32_t e = tid + kBlock * s;
+    const uint32_t e = tid + NT * s;
     const uint32_t b = base + e;
-    const R d = diag[b] + detuning<R, SITE>(c, lut, b);
-    C acc;
-    acc.x = d * v[s].x;
-    acc.y = d * v[s].y;
-    if (SITE) {
+    const R d = p.diag[b] + detuning<R, CM>(c, lut, b);
+    C acc = {d * v[s].x, d * v[s].y};
+    DriveSum<R, CM> ds;
 #pragma unroll
-      for (int p = 0; p < 8; ++p) cmad<R>(acc, c, p, (tid >> p) & 1, tile[e ^ (1u << p)]);
+    for (int q = 0; q < TB; ++q) ds.add(c, q, (tid >> q) & 1, tile[e ^ (1u << q)]);
 #pragma unroll
-      for (int q = 0; q < RB; ++q) cmad<R>(acc, c, 8 + q, (s >> q) & 1, v[s ^ (1 << q)]);
-    } else {
-      C all = {0, 0}, one = {0, 0};
-#pragma unroll
-      for (int p = 0; p < 8; ++p) {
-        const C nb = tile[e ^ (1u << p)];
-        cadd<R>(all, nb);
-        if ((tid >> p) & 1) cadd<R>(one, nb);
-      }
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const C nb = v[s ^ (1 << q)];
-        cadd<R>(all, nb);
-        if ((s >> q) & 1) cadd<R>(one, nb);
-      }
-      C zero = {all.x - one.x, all.y - one.y};
-      cmad<R>(acc, c, 0, true, one);
-      cmad<R>(acc, c, 0, false, zero);
-    }
-    if (tb) cadd<R>(acc, tb[b]);
-    if (prev) {
-      const C pv = prev[b];
-      acc.x -= cp * pv.x;
-      acc.y -= cp * pv.y;
-    }
-    out[b] = acc;
-    if (partial) dot += (double)v[s].x * (double)acc.x + (double)v[s].y * (double)acc.y;
+    for (int q = 0; q < RB; ++q) ds.add(c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
+    ds.finish(c, acc);
+    if (p.tb) cadd<R>(acc, p.tb[b]);
+    p.out[b] = acc;
+    dot += (double)v[s].x * (double)acc.x + (double)v[s].y * (double)acc.y;
   }
-  if (partial) {
-    const double t = block_sum_256(dot, red);
-    if (tid == 0) partial[blockIdx.x] = t;
+  if (p.part_norm) {
+    const double t = wg_sum<NT>(nrm, red);
+    if (tid == 0) p.part_norm[blockIdx.x] = t;
+  }
+  if (p.part_dot) {
+    const double t = wg_sum<NT>(dot, red);
+    if (tid == 0) p.part_dot[blockIdx.x] = t;
   }
 }
 
 // ----------------------------------------------------------------------------- small n
 // n < 8: one workgroup, one amplitude per thread, every flip through LDS.
-template <class R, bool SITE>
-__global__ __launch_bounds__(kBlock) void hpsi_small_kernel(
-    const StepCoef c, const R* __restrict__ diag, const Cx<R>* __restrict__ x, const double sx,
-    Cx<R>* __restrict__ out, const Cx<R>* __restrict__ prev, const double cprev,
-    double* __restrict__ partial) {
+template <class R, int CM>
+__global__ __launch_bounds__(kBlock) void hpsi_small_kernel(const StepCoef c, const PassArgs<R> p) {
   using C = Cx<R>;
   __shared__ C tile[128];
-  __shared__ R lut[SITE ? 1024 : 1];
+  __shared__ R lut[CM == kCoefSite ? 1024 : 1];
   __shared__ double red[4];
   const uint32_t tid = threadIdx.x;
   const uint32_t dim = 1u << c.n;
-  if (SITE) build_delta_lut<R>(c, lut);
+  if (CM == kCoefSite) build_delta_lut<R>(c, lut);
   C v = {0, 0};
+  double nrm = 0.0, dot = 0.0;
   if (tid < dim) {
-    v = x[tid];
-    v.x *= (R)sx;
-    v.y *= (R)sx;
+    v = form<R>(p, input_coef1(p), tid);
     tile[tid] = v;
+    if (p.u_out) {
+      p.u_out[tid] = v;
+      nrm = norm_add(0.0, (double)v.x, (double)v.y);
+    }
   }
   __syncthreads();
-  double dot = 0.0;
   if (tid < dim) {
-    const R d = diag[tid] + detuning<R, SITE>(c, lut, tid);
+    const R d = p.diag[tid] + detuning<R, CM>(c, lut, tid);
     C acc = {d * v.x, d * v.y};
-    for (int p = 0; p < c.n; ++p) cmad<R>(acc, c, SITE ? p : 0, (tid >> p) & 1, tile[tid ^ (1u << p)]);
-    if (prev) {
-      acc.x -= (R)cprev * prev[tid].x;
-      acc.y -= (R)cprev * prev[tid].y;
-    }
-    out[tid] = acc;
+    DriveSum<R, CM> ds;
+    for (int q = 0; q < c.n; ++q) ds.add(c, q, (tid >> q) & 1, tile[tid ^ (1u << q)]);
+    ds.finish(c, acc);
+    p.out[tid] = acc;
     dot = (double)v.x * (double)acc.x + (double)v.y * (double)acc.y;
   }
-  if (partial) {
+  if (p.part_norm) {
+    const double t = block_sum_256(nrm, red);
+    if (tid == 0) p.part_norm[0] = t;
+  }
+  if (p.part_dot) {
     const double t = block_sum_256(dot, red);
-    if (tid == 0) partial[0] = t;
+    if (tid == 0) p.part_dot[0] = t;
   }
 }
 
 // ----------------------------------------------------------------------------- high pass
 // Tile: bits [0, RL) and [a, a + HB - RL) of the index; flips bits in [f0, f1) only.
-template <class R, bool SITE>
-__global__ __launch_bounds__(kBlock) void hpsi_hi_kernel(
-    const StepCoef c, const Cx<R>* __restrict__ x, const double sx, Cx<R>* __restrict__ tb,
-    const int accumulate, const int a, const int f0, const int f1, const uint32_t nblk) {
+template <class R, int HB, int RL, int NT, int CM>
+__global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const PassArgs<R> p) {
   using C = Cx<R>;
-  constexpr int HB = Geo<R>::H, RL = Geo<R>::RL, G = HB - RL;
-  constexpr int A = 1 << (HB - 8);
+  constexpr int G = HB - RL;
+  constexpr int TB = ilog2(NT);
+  static_assert(HB >= TB && TB > RL, "tile shape");
+  constexpr int A = 1 << (HB - TB);
   __shared__ C tile[1 << HB];
+  __shared__ double red[NT / 64];
 
   const uint32_t tid = threadIdx.x;
-  const uint32_t blk = xcd_remap(blockIdx.x, nblk);
-  const int gap = a - RL;  // outside bits between the contiguous run and the tile's high bits
-  const uint32_t obase = ((blk & ((1u << gap) - 1u)) << RL) | ((blk >> gap) << (a + G));
+  const uint32_t blk = xcd_remap(blockIdx.x, p.nblk);
+  const int gap = p.a - RL;  // outside bits between the contiguous run and the tile's high bits
+  const uint32_t obase = ((blk & ((1u << gap) - 1u)) << RL) | ((blk >> gap) << (p.a + G));
 
-  const R s_in = (R)sx;
+  const double b1 = input_coef1(p);
   C v[A];
   uint32_t gi[A];
+  double nrm = 0.0;
 #pragma unroll
   for (int s = 0; s < A; ++s) {
-    const uint32_t e = tid + kBlock * s;
-    gi[s] = obase | (e & ((1u << RL) - 1u)) | ((e >> RL) << a);
-    C val = x[gi[s]];
-    val.x *= s_in;
-    val.y *= s_in;
-    v[s] = val;
-    tile[e] = val;
+    const uint32_t e = tid + NT * s;
+    gi[s] = obase | (e & ((1u << RL) - 1u)) | ((e >> RL) << p.a);
+    v[s] = form<R>(p, b1, gi[s]);
+    tile[e] = v[s];
+  }
+  if (p.u_out) {
+#pragma unroll
+    for (int s = 0; s < A; ++s) {
+      p.u_out[gi[s]] = v[s];
+      nrm = norm_add(nrm, (double)v[s].x, (double)v[s].y);
+    }
   }
   __syncthreads();
 
 #pragma unroll
   for (int s = 0; s < A; ++s) {
-    const uint32_t e = tid + kBlock * s;
+    const uint32_t e = tid + NT * s;
     C acc = {0, 0};
-    C all = {0, 0}, one = {0, 0};
+    DriveSum<R, CM> ds;
 #pragma unroll
     for (int eb = RL; eb < HB; ++eb) {
-      const int p = a + eb - RL;
-      if (p < f0 || p >= f1) continue;
-      C nb;
-      if (eb < 8) nb = tile[e ^ (1u << eb)];
-      else nb = v[s ^ (1 << (eb - 8))];
-      const bool bit = (e >> eb) & 1u;
-      if (SITE) {
-        cmad<R>(acc, c, p, bit, nb);
-      } else {
-        cadd<R>(all, nb);
-        if (bit) cadd<R>(one, nb);
-      }
+      const int q = p.a + eb - RL;
+      if (q < p.f0 || q >= p.f1) continue;
+      const C nb = eb < TB ? tile[e ^ (1u << eb)] : v[s ^ (1 << (eb - TB))];
+      ds.add(c, q, (e >> eb) & 1u, nb);
     }
-    if (!SITE) {
-      C zero = {all.x - one.x, all.y - one.y};
-      cmad<R>(acc, c, 0, true, one);
-      cmad<R>(acc, c, 0, false, zero);
-    }
-    if (accumulate) cadd<R>(acc, tb[gi[s]]);
-    tb[gi[s]] = acc;
+    ds.finish(c, acc);
+    if (p.accumulate) cadd<R>(acc, p.tb[gi[s]]);
+    p.tb[gi[s]] = acc;
+  }
+  if (p.part_norm) {
+    const double t = wg_sum<NT>(nrm, red);
+    if (tid == 0) p.part_norm[blockIdx.x] = t;
   }
 }
 
-template <class R, int LB, bool SITE>
-void launch_lo(const StepCoef& c, const void* diag, const void* x, double sx, void* out,
-               const void* tb, const void* prev, double cprev, double* partial, int n,
-               hipStream_t s) {
-  const uint32_t nblk = 1u << (n - LB);
-  hipLaunchKernelGGL((hpsi_lo_kernel<R, LB, SITE>), dim3(nblk), dim3(kBlock), 0, s, c,
-                     (const R*)diag, (const Cx<R>*)x, sx, (Cx<R>*)out, (const Cx<R>*)tb,
-                     (const Cx<R>*)prev, cprev, partial, nblk);
+template <class R, int LB, int CM>
+void launch_lo(const StepCoef& c, PassArgs<R> p, int n, hipStream_t s) {
+  constexpr int NT = Geo<R>::NL < (1 << LB) ? Geo<R>::NL : (1 << LB);
+  p.nblk = 1u << (n - LB);
+  hipLaunchKernelGGL((hpsi_lo_kernel<R, LB, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p);
 }
 
-template <class R, bool SITE>
-void launch_lo_any(int lb, const StepCoef& c, const void* diag, const void* x, double sx,
-                   void* out, const void* tb, const void* prev, double cprev, double* partial,
-                   int n, hipStream_t s) {
+template <class R, int CM>
+void launch_lo_any(int lb, const StepCoef& c, const PassArgs<R>& p, int n, hipStream_t s) {
   switch (lb) {
-    case 8: launch_lo<R, 8, SITE>(c, diag, x, sx, out, tb, prev, cprev, partial, n, s); break;
-    case 9: launch_lo<R, 9, SITE>(c, diag, x, sx, out, tb, prev, cprev, partial, n, s); break;
-    case 10: launch_lo<R, 10, SITE>(c, diag, x, sx, out, tb, prev, cprev, partial, n, s); break;
-    case 11: launch_lo<R, 11, SITE>(c, diag, x, sx, out, tb, prev, cprev, partial, n, s); break;
-    case 12: launch_lo<R, 12, SITE>(c, diag, x, sx, out, tb, prev, cprev, partial, n, s); break;
+    case 8: launch_lo<R, 8, CM>(c, p, n, s); break;
+    case 9: launch_lo<R, 9, CM>(c, p, n, s); break;
+    case 10: launch_lo<R, 10, CM>(c, p, n, s); break;
+    case 11: launch_lo<R, 11, CM>(c, p, n, s); break;
+    case 12: launch_lo<R, 12, CM>(c, p, n, s); break;
     default:
-      if constexpr (Geo<R>::L >= 13) {
-        launch_lo<R, 13, SITE>(c, diag, x, sx, out, tb, prev, cprev, partial, n, s);
-      }
+      if constexpr (Geo<R>::L >= 13) launch_lo<R, 13, CM>(c, p, n, s);
       break;
   }
 }
 
-template <class R, bool SITE>
-hipError_t apply_t(int n, const StepCoef& c, const void* diag, const void* x, double sx,
-                   void* out, const void* prev, double cprev, void* tbuf, double* partial,
-                   hipStream_t s) {
+template <class R, int CM>
+void launch_hi(int rl, const StepCoef& c, const PassArgs<R>& p, hipStream_t s) {
+  constexpr int HB = Geo<R>::H, NT = Geo<R>::NH;
+  if (rl == Geo<R>::RL)
+    hipLaunchKernelGGL((hpsi_hi_kernel<R, HB, Geo<R>::RL, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p);
+  else
+    hipLaunchKernelGGL((hpsi_hi_kernel<R, HB, Geo<R>::RLW, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p);
+}
+
+template <class R, int CM>
+hipError_t sweep_t(int n, const StepCoef& c, const void* diag, const SweepIn& in, void* out,
+                   void* tbuf, const SweepOut& so, int part, hipStream_t s) {
+  PassArgs<R> base{};
+  base.x0 = (const Cx<R>*)in.x0;
+  base.x1 = (const Cx<R>*)in.x1;
+  base.x2 = (const Cx<R>*)in.x2;
+  base.a0 = in.a0;
+  base.a1 = in.a1;
+  base.a2 = in.a2;
+  base.dot = in.dot;
+  base.dot_coef = in.dot_coef;
+  base.diag = (const R*)diag;
+  base.out = (Cx<R>*)out;
+
+  const bool first = part != kLaterPasses, later = part != kFirstPass;
   if (n < 8) {
-    hipLaunchKernelGGL((hpsi_small_kernel<R, SITE>), dim3(1), dim3(kBlock), 0, s, c,
-                       (const R*)diag, (const Cx<R>*)x, sx, (Cx<R>*)out, (const Cx<R>*)prev,
-                       cprev, partial);
+    if (!first) return hipSuccess;
+    PassArgs<R> p = base;
+    p.u_out = (Cx<R>*)so.u_out;
+    p.part_norm = so.part_norm;
+    p.part_dot = so.part_dot;
+    hipLaunchKernelGGL((hpsi_small_kernel<R, CM>), dim3(1), dim3(kBlock), 0, s, c, p);
     return hipGetLastError();
   }
   const TilePlan plan = make_tile_plan(sizeof(R) == 8 ? kC128 : kC64, n);
+  // the formed input, once stored, is the plain input of every later pass
+  const bool forming = in.x1 || in.x2 || in.a0 != 1.0 || in.dot;
+  if (forming && plan.n_hi_passes > 0 && !so.u_out) return hipErrorInvalidValue;
+  const Cx<R>* stored = so.u_out ? (const Cx<R>*)so.u_out : (const Cx<R>*)in.x0;
   for (int i = 0; i < plan.n_hi_passes; ++i) {
-    const uint32_t nblk = 1u << (n - plan.hi_bits);
-    hipLaunchKernelGGL((hpsi_hi_kernel<R, SITE>), dim3(nblk), dim3(kBlock), 0, s, c,
-                       (const Cx<R>*)x, sx, (Cx<R>*)tbuf, i > 0 ? 1 : 0, plan.tile_a[i],
-                       plan.flip_lo[i], plan.flip_hi[i], nblk);
+    if ((i == 0 && !first) || (i > 0 && !later)) continue;
+    PassArgs<R> p = base;
+    if (i > 0) {
+      p.x0 = stored;
+      p.x1 = p.x2 = nullptr;
+      p.a0 = 1.0;
+      p.dot = nullptr;
+    } else {
+      p.u_out = (Cx<R>*)so.u_out;
+      p.part_norm = so.part_norm;
+    }
+    p.tb = (Cx<R>*)tbuf;
+    p.accumulate = i > 0 ? 1 : 0;
+    p.a = plan.tile_a[i];
+    p.f0 = plan.flip_lo[i];
+    p.f1 = plan.flip_hi[i];
+    p.nblk = 1u << (n - plan.hi_bits);
+    launch_hi<R, CM>(plan.run_bits[i], c, p, s);
   }
-  launch_lo_any<R, SITE>(plan.lo_bits, c, diag, x, sx, out,
-                         plan.n_hi_passes > 0 ? tbuf : nullptr, prev, cprev, partial, n, s);
+  if ((plan.n_hi_passes > 0 && !later) || (plan.n_hi_passes == 0 && !first)) return hipGetLastError();
+  PassArgs<R> p = base;
+  if (plan.n_hi_passes > 0) {
+    p.x0 = stored;
+    p.x1 = p.x2 = nullptr;
+    p.a0 = 1.0;
+    p.dot = nullptr;
+    p.tb = (Cx<R>*)tbuf;
+  } else {
+    p.u_out = (Cx<R>*)so.u_out;
+    p.part_norm = so.part_norm;
+  }
+  p.part_dot = so.part_dot;
+  launch_lo_any<R, CM>(plan.lo_bits, c, p, n, s);
   return hipGetLastError();
+}
+
+template <class R>
+hipError_t sweep_r(int n, const StepCoef& c, const void* diag, const SweepIn& in, void* out,
+                   void* tbuf, const SweepOut& so, int part, hipStream_t s) {
+  switch (c.mode) {
+    case kCoefReal: return sweep_t<R, kCoefReal>(n, c, diag, in, out, tbuf, so, part, s);
+    case kCoefSite: return sweep_t<R, kCoefSite>(n, c, diag, in, out, tbuf, so, part, s);
+    default: return sweep_t<R, kCoefUniform>(n, c, diag, in, out, tbuf, so, part, s);
+  }
 }
 
 }  // namespace
@@ -297,38 +450,58 @@ TilePlan make_tile_plan(int prec, int n) {
   TilePlan p{};
   p.n = n;
   const int L = prec == kC128 ? Geo<double>::L : Geo<float>::L;
+  const int rl = prec == kC128 ? Geo<double>::RL : Geo<float>::RL;
+  const int rlw = prec == kC128 ? Geo<double>::RLW : Geo<float>::RLW;
   p.hi_bits = prec == kC128 ? Geo<double>::H : Geo<float>::H;
-  p.r_bits = prec == kC128 ? Geo<double>::RL : Geo<float>::RL;
   p.lo_bits = n < L ? n : L;
   p.n_hi_passes = 0;
-  const int g = p.hi_bits - p.r_bits;
+  const int g = p.hi_bits - rl;
   for (int f0 = p.lo_bits; f0 < n; f0 += g) {
     const int f1 = f0 + g < n ? f0 + g : n;
+    // a narrow last pass takes a wider contiguous run (better coalescing), a full one the
+    // narrow run that leaves the most bits for flips
+    const int r = (f1 - f0 <= p.hi_bits - rlw && n - (p.hi_bits - rlw) >= rlw) ? rlw : rl;
+    const int gw = p.hi_bits - r;
     int a = f0;
-    if (a + g > n) a = n - g;  // keep the whole tile inside the index; extra bits are not flipped
+    if (a + gw > n) a = n - gw;  // keep the whole tile inside the index; extra bits are not flipped
     p.flip_lo[p.n_hi_passes] = f0;
     p.flip_hi[p.n_hi_passes] = f1;
     p.tile_a[p.n_hi_passes] = a;
+    p.run_bits[p.n_hi_passes] = r;
     ++p.n_hi_passes;
   }
   return p;
 }
 
-int64_t hpsi_num_partials(int prec, int n) {
+int64_t sweep_num_partials(int prec, int n) {
+  if (n < 8) return 1;
+  const TilePlan p = make_tile_plan(prec, n);
+  const int64_t lo = int64_t(1) << (n - p.lo_bits);
+  const int64_t hi = p.n_hi_passes ? int64_t(1) << (n - p.hi_bits) : 0;
+  return lo > hi ? lo : hi;
+}
+
+int64_t sweep_norm_partials(int prec, int n) {
+  if (n < 8) return 1;
+  const TilePlan p = make_tile_plan(prec, n);
+  return p.n_hi_passes ? int64_t(1) << (n - p.hi_bits) : int64_t(1) << (n - p.lo_bits);
+}
+
+int64_t sweep_dot_partials(int prec, int n) {
   if (n < 8) return 1;
   const TilePlan p = make_tile_plan(prec, n);
   return int64_t(1) << (n - p.lo_bits);
 }
 
-hipError_t hpsi_apply(int prec, int n, const StepCoef& c, const void* diag, const void* x,
-                      double sx, void* out, const void* prev, double cprev, void* tbuf,
-                      double* partial, hipStream_t s) {
-  if (prec == kC128) {
-    return c.site ? apply_t<double, true>(n, c, diag, x, sx, out, prev, cprev, tbuf, partial, s)
-                  : apply_t<double, false>(n, c, diag, x, sx, out, prev, cprev, tbuf, partial, s);
-  }
-  return c.site ? apply_t<float, true>(n, c, diag, x, sx, out, prev, cprev, tbuf, partial, s)
-                : apply_t<float, false>(n, c, diag, x, sx, out, prev, cprev, tbuf, partial, s);
+int sweep_passes(int prec, int n) {
+  if (n < 8) return 1;
+  return 1 + make_tile_plan(prec, n).n_hi_passes;
+}
+
+hipError_t hpsi_sweep(int prec, int n, const StepCoef& c, const void* diag, const SweepIn& in,
+                      void* out, void* tbuf, const SweepOut& so, int part, hipStream_t s) {
+  if (prec == kC128) return sweep_r<double>(n, c, diag, in, out, tbuf, so, part, s);
+  return sweep_r<float>(n, c, diag, in, out, tbuf, so, part, s);
 }
 
 }  // namespace rsv

@@ -21,7 +21,7 @@ constexpr int kOccStride = 1 + kChunkBits;  // per chunk: total, then one sum pe
 
 template <class R>
 __device__ __forceinline__ double prob(const Cx<R>& v) {
-  return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  return norm_add(0.0, (double)v.x, (double)v.y);
 }
 
 template <class R>

@@ -24,10 +24,12 @@ inline size_t real_bytes(int prec) { return prec == kC128 ? 8 : 4; }
 // One constant Hamiltonian H_k of eq. (3) with the drive phase, by bit position p:
 //   (H x)_b = (E_b - sum_p delta[p] b_p) x_b + sum_p c_p(b_p) x_{b ^ 2^p}
 // with c_p(1) = up[p] = Omega/2 e^{-i phi} (= <1|h|0>) and c_p(0) = dn[p] = Omega/2 e^{+i phi}.
-// site == 0 means every bit shares index 0 (a global drive).
+// mode kCoefUniform / kCoefReal: every bit shares index 0 (a global drive; kCoefReal when
+// phi = 0 so that up = dn is real); kCoefSite: per-bit coefficients.
+enum CoefMode : int { kCoefUniform = 0, kCoefReal = 1, kCoefSite = 2 };
 struct StepCoef {
   int n;
-  int site;
+  int mode;
   double up_re[kMaxAtoms], up_im[kMaxAtoms];
   double dn_re[kMaxAtoms], dn_im[kMaxAtoms];
   double delta[kMaxAtoms];
@@ -42,22 +44,43 @@ struct CombineCoef {
 
 // --------------------------------------------------------------------------- H|psi>
 // Tile geometry of the H|psi> passes for a precision: the low pass covers bits [0, lo_bits);
-// each high pass covers up to hi_bits - r_bits high bits plus r_bits contiguous low bits.
+// high pass i covers bits [tile_a, tile_a + hi_bits - run_bits) plus run_bits contiguous low
+// bits and flips [flip_lo, flip_hi).
 struct TilePlan {
-  int n, lo_bits, hi_bits, r_bits;
+  int n, lo_bits, hi_bits;
   int n_hi_passes;
-  int flip_lo[kMaxAtoms], flip_hi[kMaxAtoms], tile_a[kMaxAtoms];
+  int flip_lo[kMaxAtoms], flip_hi[kMaxAtoms], tile_a[kMaxAtoms], run_bits[kMaxAtoms];
 };
 TilePlan make_tile_plan(int prec, int n);
 
-// Number of per-workgroup partial sums hpsi_apply writes (0 when no partials requested).
-int64_t hpsi_num_partials(int prec, int n);
+// Input of one H sweep: u = a0 x0 + (a1 + dot_coef * dot[0]) x1 + a2 x2 (x1, x2, dot may
+// be null).  With only x0 and a0 = 1 the sweep applies H to a stored vector.
+struct SweepIn {
+  const void* x0;
+  const void* x1;
+  const void* x2;
+  double a0, a1, a2;
+  const double* dot;
+  double dot_coef;
+};
+// Optional outputs: u_out stores the formed u (required when the sweep forms u and has
+// more than one pass); part_norm / part_dot receive per-workgroup FP64 partial sums of |u|^2
+// and Re<u, H u>.
+struct SweepOut {
+  void* u_out;
+  double* part_norm;
+  double* part_dot;
+};
+enum SweepPart : int { kAllPasses = 0, kFirstPass = 1, kLaterPasses = 2 };
 
-// out = sx * H x + (prev ? -cprev * prev : 0), optionally partial[wg] = Re<sx x, out> per
-// workgroup of the low pass (FP64).  tbuf (one vector) is required when n > lo_bits.
-hipError_t hpsi_apply(int prec, int n, const StepCoef& c, const void* diag, const void* x,
-                      double sx, void* out, const void* prev, double cprev, void* tbuf,
-                      double* partial, hipStream_t s);
+// out = H u over all passes of the tile plan (or only the first / only the later ones);
+// tbuf (one vector) holds the high-bit partial when n > lo_bits.
+hipError_t hpsi_sweep(int prec, int n, const StepCoef& c, const void* diag, const SweepIn& in,
+                      void* out, void* tbuf, const SweepOut& so, int part, hipStream_t s);
+int64_t sweep_num_partials(int prec, int n);   // the largest partial count of any pass
+int64_t sweep_norm_partials(int prec, int n);  // partials of |u|^2 (first pass)
+int64_t sweep_dot_partials(int prec, int n);   // partials of Re<u, H u> (low pass)
+int sweep_passes(int prec, int n);
 
 // --------------------------------------------------------------------------- diagonal
 // E_b = sum_{p<q} Ub[p][q] b_p b_q for all b < 2^n; Ub is 32x32 FP64, bit-indexed, on device.
@@ -65,9 +88,6 @@ hipError_t diag_build(int prec, int n, const double* d_ub, void* diag, hipStream
 
 // --------------------------------------------------------------------------- vectors
 int64_t vec_num_partials(int prec, int n);
-// u = w - alpha * sv * v (alpha read from d_alpha[0]); partial ||u||^2.
-hipError_t lanczos_update(int prec, int n, const void* w, const void* v, double sv,
-                          const double* d_alpha, void* u, double* partial, hipStream_t s);
 // out = sum_l coef_l x_l; partial ||out||^2.
 hipError_t krylov_combine(int prec, int n, const CombineCoef& c, void* out, double* partial,
                           hipStream_t s);
@@ -95,5 +115,8 @@ hipError_t sample(int prec, int n, const void* x, uint64_t seed, int shots, doub
 int tridiag_expm(int m, const double* alpha, const double* beta, double tau, double* y_re,
                  double* y_im, double* work);
 size_t tridiag_work_doubles(int m);
+// |[exp(-i tau T) e_1]_{m-1}| only (rows 0 and m-1 of the eigenvectors): the convergence test.
+int tridiag_expm_last(int m, const double* alpha, const double* beta, double tau,
+                      double* last_abs, double* work);
 
 }  // namespace rsv

@@ -6,6 +6,8 @@
 // (at most 64 x 64), so the active block is kept as a dense matrix and every rotation
 // updates only the rows and columns it touches inside the band.  With T = Q diag(l) Q^T:
 //   y = Q exp(-i tau diag(l)) Q^T e_1,  y_j = sum_k Q[j][k] exp(-i tau l_k) Q[0][k].
+// The convergence test needs only y_{m-1}, i.e. rows 0 and m-1 of Q: the "last" variant
+// accumulates just those two rows, O(m) per rotation less work.
 #include <cfloat>
 #include <cmath>
 
@@ -38,14 +40,10 @@ inline bool negligible(double off, double d0, double d1) {
          std::fabs(off) < DBL_MIN;
 }
 
-}  // namespace
-
-// work: 2*m*m + 2*m doubles.  On success returns 0 and the eigenpairs were consumed into y.
-int tridiag_expm(int m, const double* alpha, const double* beta, double tau, double* y_re,
-                 double* y_im, double* work) {
-  if (m <= 0 || m > kMaxKrylov) return -1;
-  double* t = work;          // m x m, row-major
-  double* q = work + m * m;  // m x m, row-major; columns are eigenvectors
+// Eigenvalues into the diagonal of t (m x m), eigenvectors into the columns of q.  With
+// all_rows false only rows 0 and m-1 of q are kept up to date.
+int tridiag_eig(int m, const double* alpha, const double* beta, double* t, double* q,
+                bool all_rows) {
   for (int i = 0; i < m * m; ++i) t[i] = q[i] = 0.0;
   for (int i = 0; i < m; ++i) {
     t[i * m + i] = alpha[i];
@@ -53,6 +51,11 @@ int tridiag_expm(int m, const double* alpha, const double* beta, double tau, dou
     if (i + 1 < m) t[i * m + i + 1] = t[(i + 1) * m + i] = beta[i];
   }
   auto T = [&](int i, int j) -> double& { return t[i * m + j]; };
+  auto rotate_q = [&](int i, int k, double c, double s) {
+    const double a0 = q[i * m + k], a1 = q[i * m + k + 1];
+    q[i * m + k] = c * a0 - s * a1;
+    q[i * m + k + 1] = s * a0 + c * a1;
+  };
 
   int hi = m - 1, iter = 0;
   while (hi > 0) {
@@ -89,10 +92,11 @@ int tridiag_expm(int m, const double* alpha, const double* beta, double tau, dou
         T(i, k) = c * a0 - s * a1;
         T(i, k + 1) = s * a0 + c * a1;
       }
-      for (int i = 0; i < m; ++i) {  // Q <- Q G
-        const double a0 = q[i * m + k], a1 = q[i * m + k + 1];
-        q[i * m + k] = c * a0 - s * a1;
-        q[i * m + k + 1] = s * a0 + c * a1;
+      if (all_rows) {
+        for (int i = 0; i < m; ++i) rotate_q(i, k, c, s);  // Q <- Q G
+      } else {
+        rotate_q(0, k, c, s);
+        if (m > 1) rotate_q(m - 1, k, c, s);
       }
       if (k + 1 < hi) {
         x = T(k + 1, k);
@@ -100,10 +104,23 @@ int tridiag_expm(int m, const double* alpha, const double* beta, double tau, dou
       }
     }
   }
+  return 0;
+}
+
+}  // namespace
+
+// work: 2*m*m + 2*m doubles.
+int tridiag_expm(int m, const double* alpha, const double* beta, double tau, double* y_re,
+                 double* y_im, double* work) {
+  if (m <= 0 || m > kMaxKrylov) return -1;
+  double* t = work;
+  double* q = work + m * m;
+  const int rc = tridiag_eig(m, alpha, beta, t, q, true);
+  if (rc) return rc;
   double* er = work + 2 * m * m;  // Q[0][k] exp(-i tau l_k)
   double* ei = er + m;
   for (int k = 0; k < m; ++k) {
-    const double ph = -tau * T(k, k);
+    const double ph = -tau * t[k * m + k];
     er[k] = q[k] * std::cos(ph);
     ei[k] = q[k] * std::sin(ph);
   }
@@ -116,6 +133,24 @@ int tridiag_expm(int m, const double* alpha, const double* beta, double tau, dou
     y_re[j] = sr;
     y_im[j] = si;
   }
+  return 0;
+}
+
+int tridiag_expm_last(int m, const double* alpha, const double* beta, double tau,
+                      double* last_abs, double* work) {
+  if (m <= 0 || m > kMaxKrylov) return -1;
+  double* t = work;
+  double* q = work + m * m;
+  const int rc = tridiag_eig(m, alpha, beta, t, q, false);
+  if (rc) return rc;
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const double ph = -tau * t[k * m + k];
+    const double w = q[(m - 1) * m + k] * q[k];
+    sr += w * std::cos(ph);
+    si += w * std::sin(ph);
+  }
+  *last_abs = std::hypot(sr, si);
   return 0;
 }
 

@@ -1,4 +1,4 @@
-// Streaming vector kernels of the Lanczos recurrence (Sec. III.A) and the Krylov
+// Streaming vector kernels: norms, reductions and the Krylov
 // combination psi_{k+1} = |psi_k| V_m exp(-i dt T_m) e_1 (eq. 6).
 //
 // All are HBM-bound single sweeps.  Every reduction is two-stage and deterministic: each
@@ -11,27 +11,6 @@ namespace rsv {
 namespace {
 
 constexpr int kPerThread = 8;
-
-template <class R>
-__global__ __launch_bounds__(kBlock) void lanczos_update_kernel(
-    const Cx<R>* __restrict__ w, const Cx<R>* __restrict__ v, const double sv,
-    const double* __restrict__ d_alpha, Cx<R>* __restrict__ u, double* __restrict__ partial,
-    const size_t count) {
-  __shared__ double red[4];
-  const double a = d_alpha[0] * sv;
-  double acc = 0.0;
-  const size_t stride = (size_t)gridDim.x * kBlock;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
-    const Cx<R> wi = w[i], vi = v[i];
-    Cx<R> r;
-    r.x = (R)((double)wi.x - a * (double)vi.x);
-    r.y = (R)((double)wi.y - a * (double)vi.y);
-    u[i] = r;
-    acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
-  }
-  const double t = block_sum_256(acc, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void combine_kernel(const CombineCoef c,
@@ -55,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombineCoef c,
     r.x = (R)re;
     r.y = (R)im;
     out[i] = r;
-    acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+    acc = norm_add(acc, (double)r.x, (double)r.y);
   }
   const double t = block_sum_256(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -70,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void norm2_kernel(const Cx<R>* __restrict__
   const size_t stride = (size_t)gridDim.x * kBlock;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
     const Cx<R> xi = x[i];
-    acc += (double)xi.x * (double)xi.x + (double)xi.y * (double)xi.y;
+    acc = norm_add(acc, (double)xi.x, (double)xi.y);
   }
   const double t = block_sum_256(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -109,21 +88,6 @@ __global__ __launch_bounds__(kBlock) void convert_kernel(const Cx<RS>* __restric
 int64_t vec_num_partials(int prec, int n) {
   (void)prec;
   return stream_grid(size_t(1) << n, kPerThread);
-}
-
-hipError_t lanczos_update(int prec, int n, const void* w, const void* v, double sv,
-                          const double* d_alpha, void* u, double* partial, hipStream_t s) {
-  const size_t count = size_t(1) << n;
-  const uint32_t g = stream_grid(count, kPerThread);
-  if (prec == kC128)
-    hipLaunchKernelGGL(lanczos_update_kernel<double>, dim3(g), dim3(kBlock), 0, s,
-                       (const double2*)w, (const double2*)v, sv, d_alpha, (double2*)u, partial,
-                       count);
-  else
-    hipLaunchKernelGGL(lanczos_update_kernel<float>, dim3(g), dim3(kBlock), 0, s,
-                       (const float2*)w, (const float2*)v, sv, d_alpha, (float2*)u, partial,
-                       count);
-  return hipGetLastError();
 }
 
 hipError_t krylov_combine(int prec, int n, const CombineCoef& c, void* out, double* partial,

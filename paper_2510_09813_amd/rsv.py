@@ -272,3 +272,119 @@ def rsv_tridiag_expm(alpha, beta, tau: float):
     _check(lib().rsv_tridiag_expm(m, a.ctypes.data_as(pd), b.ctypes.data_as(pd) if m > 1 else None,
                                   float(tau), yr.ctypes.data_as(pd), yi.ctypes.data_as(pd)))
     return yr + 1j * yi
+
+
+# ------------------------------------------------------------------------- serving
+class ServerOpts(C.Structure):
+    _fields_ = [("n_lanes", C.c_int), ("arena_bytes", C.c_size_t), ("max_queue", C.c_int)]
+
+
+class JobDesc(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("xyz_um", C.POINTER(C.c_double)), ("c6", C.c_double),
+                ("prec", C.c_int), ("pulses", Pulses), ("opts", EvolveOpts),
+                ("psi0_host", C.c_void_p), ("n_shots", C.c_int), ("seed", C.c_uint64),
+                ("return_state", C.c_int), ("tag", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("job_id", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_int),
+                ("n_atoms", C.c_int), ("n_shots", C.c_int), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_end", C.c_double), ("stats", Stats),
+                ("occupations", C.POINTER(C.c_double)), ("samples", C.POINTER(C.c_uint64)),
+                ("state", C.c_void_p), ("error", C.c_char * 160)]
+
+
+def _server_sigs(L):
+    vp = C.c_void_p
+    sig = {
+        "rsv_server_create": (C.c_int, [vp, C.POINTER(ServerOpts), C.POINTER(vp)]),
+        "rsv_server_job_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int]),
+        "rsv_server_submit": (C.c_int, [vp, C.POINTER(JobDesc), C.POINTER(C.c_uint64)]),
+        "rsv_server_poll": (C.c_int, [vp, C.POINTER(Completion), C.c_int, C.POINTER(C.c_int),
+                                      C.c_int]),
+        "rsv_server_release": (None, [vp, C.POINTER(Completion)]),
+        "rsv_server_cancel": (C.c_int, [vp, C.c_uint64]),
+        "rsv_server_status": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                        C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
+        "rsv_server_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+EXPORTED += ["rsv_server_create", "rsv_server_job_bytes", "rsv_server_submit", "rsv_server_poll",
+             "rsv_server_release", "rsv_server_cancel", "rsv_server_status", "rsv_server_destroy"]
+
+
+def _slib():
+    L = lib()
+    if not getattr(L, "_server_sigs", False):
+        _server_sigs(L)
+        L._server_sigs = True
+    return L
+
+
+def rsv_server_create(ctx, n_lanes: int = 4, arena_bytes: int = 0, max_queue: int = 0):
+    h = C.c_void_p()
+    opts = ServerOpts(n_lanes, arena_bytes, max_queue)
+    _check(_slib().rsv_server_create(ctx, C.byref(opts), C.byref(h)))
+    return h
+
+
+def rsv_server_job_bytes(n_atoms: int, kmax: int, precision="c64", n_shots: int = 0) -> int:
+    return int(_slib().rsv_server_job_bytes(n_atoms, kmax, PRECISIONS.get(precision, precision),
+                                            n_shots))
+
+
+def rsv_server_submit(srv, xyz, c6, pulses: PulseArrays, opts: EvolveOpts, precision="c64",
+                      psi0=None, n_shots: int = 0, seed: int = 0, return_state: bool = False,
+                      tag: int = 0) -> int:
+    xyz = _f64(xyz).reshape(-1, 3)
+    buf = None if psi0 is None else np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+    jd = JobDesc(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), float(c6),
+                 PRECISIONS.get(precision, precision), pulses.struct, opts,
+                 buf.ctypes.data if buf is not None else None, n_shots, seed, int(return_state), tag)
+    jid = C.c_uint64()
+    _check(_slib().rsv_server_submit(srv, C.byref(jd), C.byref(jid)))
+    return int(jid.value)
+
+
+def rsv_server_poll(srv, max_n: int = 64, timeout_ms: int = -1):
+    """Completed jobs as dicts (arrays copied out; the server's copies are released)."""
+    arr = (Completion * max_n)()
+    got = C.c_int()
+    _check(_slib().rsv_server_poll(srv, arr, max_n, C.byref(got), timeout_ms))
+    out = []
+    for i in range(got.value):
+        c = arr[i]
+        d = {"job_id": int(c.job_id), "tag": int(c.tag), "status": int(c.status),
+             "n_atoms": int(c.n_atoms), "t_submit": c.t_submit, "t_start": c.t_start,
+             "t_end": c.t_end, "stats": c.stats.as_dict(), "error": c.error.decode(errors="replace"),
+             "occupations": None, "samples": None, "state": None}
+        if c.occupations:
+            d["occupations"] = np.ctypeslib.as_array(c.occupations, (c.n_atoms,)).copy()
+        if c.samples and c.n_shots > 0:
+            d["samples"] = np.ctypeslib.as_array(c.samples, (c.n_shots,)).copy()
+        if c.state:
+            dim = 1 << c.n_atoms
+            raw = np.ctypeslib.as_array(C.cast(c.state, C.POINTER(C.c_double)), (2 * dim,))
+            d["state"] = raw.view(np.complex128).copy()
+        _slib().rsv_server_release(srv, C.byref(arr[i]))
+        out.append(d)
+    return out
+
+
+def rsv_server_cancel(srv, job_id: int):
+    _check(_slib().rsv_server_cancel(srv, job_id))
+
+
+def rsv_server_status(srv):
+    q, r, d, used = C.c_int(), C.c_int(), C.c_int(), C.c_size_t()
+    _check(_slib().rsv_server_status(srv, C.byref(q), C.byref(r), C.byref(d), C.byref(used)))
+    return {"queued": q.value, "running": r.value, "done": d.value, "arena_used": used.value}
+
+
+def rsv_server_destroy(srv):
+    _slib().rsv_server_destroy(srv)

@@ -154,7 +154,7 @@ def random27(seed: int = 0, n_atoms: int = 27, precision: str = "c128") -> Workl
     omega, delta, t_ns = sweep_pulses(500, 3000, omax, dmax)
     tol = 1e-10 if precision == "c128" else 1e-7
     return Workload(f"random{n_atoms}", xyz, C6_RB, omega, delta, None, t_ns, 10, tol=tol,
-                    kmax=30, precision=precision)
+                    kmax=48, precision=precision)
 
 
 def triangular30(n_atoms: int = 30, precision: str = "c64") -> Workload:

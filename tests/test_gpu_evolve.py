@@ -248,3 +248,46 @@ def test_observables_of_device_states(ctx, n, prec):
     lv = np.array([[(int(b) >> (n - 1 - i)) & 1 for i in range(n)] for b in shots])
     sig = np.sqrt(np.maximum(occ * (1 - occ), 1e-12) / len(shots))
     assert np.all(np.abs(lv.mean(0) - occ) <= 5 * sig + 1e-12)
+
+
+def test_n28_triangular_c64_against_c128(ctx):
+    """The 5x6 triangular pattern at 28 atoms: complex64 storage with FP64 Lanczos scalars
+    against complex128, 6 quench steps (dt = 5 ns, kmax 20)."""
+    w = wl.triangular30(n_atoms=28, precision="c128")
+    a, occ_a, st_a, r1 = gpu_run(ctx, w, "c128", first=0, steps=6)
+    rsv.rsv_result_destroy(r1)
+    b, occ_b, st_b, r2 = gpu_run(ctx, w, "c64", first=0, steps=6, tol=1e-7)
+    rsv.rsv_result_destroy(r2)
+    assert st_a["krylov_max"] <= 20 and st_b["krylov_max"] <= 20
+    assert observables.fidelity_loss(a, b) <= 1e-6
+    assert np.abs(occ_a - occ_b).max() <= 1e-5
+
+
+def test_n30_c64_capacity_and_time_reversal(ctx):
+    """N = 30 in complex64 on one GPU (8 GiB per vector): 3 quench steps forward, then the
+    reversed samples with Omega, delta and C negated bring the state back to |0...0>."""
+    import torch
+    torch.cuda.empty_cache()
+    w = wl.triangular30(n_atoms=30, precision="c64")
+    need = rsv.rsv_workspace_bytes(30, w.kmax, "c64")
+    free, _ = torch.cuda.mem_get_info()
+    assert need < free, (need, free)
+    reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c64")
+    psi = torch.zeros(1 << 30, dtype=torch.complex64, device="cuda:0")
+    psi[0] = 1
+    st = rsv.rsv_evolve_device(reg, rsv.PulseArrays(w.omega, w.delta),
+                               rsv.evolve_opts(w.dt_ns, 1e-7, w.kmax, 12, 0, 3), psi)
+    rsv.rsv_register_destroy(reg)
+    assert st.steps == 3 and abs(st.norm_final - 1.0) < 1e-5
+    occ = rsv.rsv_occupations_device(ctx, 30, psi, "c64")
+    assert np.all(occ > 0) and occ.sum() < 1.0
+    K = w.n_steps
+    reg = rsv.rsv_register_create(ctx, w.xyz, -w.c6, "c64")
+    back = rsv.PulseArrays(-w.omega[::-1].copy(), -w.delta[::-1].copy())
+    rsv.rsv_evolve_device(reg, back, rsv.evolve_opts(w.dt_ns, 1e-7, w.kmax, 12, K - 3, 3), psi)
+    rsv.rsv_register_destroy(reg)
+    p0 = float(abs(psi[0].item()) ** 2)
+    nrm2 = float(torch.linalg.vector_norm(psi.to(torch.complex128)).item() ** 2)
+    assert 1.0 - p0 / nrm2 <= 1e-6
+    del psi
+    torch.cuda.empty_cache()
