@@ -129,7 +129,7 @@ def serving_leg(rsv, wl, ctx, n_jobs, lanes):
         seq_lat.append(t_free - a)
 
     arena = 2 * sum(sorted(rsv.rsv_server_job_bytes(w.n_atoms, w.kmax, "c64", 0) for w in jobs)[-lanes:])
-    srv = rsv.rsv_server_create(ctx, n_lanes=lanes, arena_bytes=arena)
+    srv = rsv.rsv_server_create(ctx, n_lanes=lanes, arena_bytes=arena, pack_max_atoms=13)
     done = []
     try:
         pulses = [rsv.PulseArrays(w.omega, w.delta) for w in jobs]
@@ -165,10 +165,51 @@ def serving_leg(rsv, wl, ctx, n_jobs, lanes):
         "sequential_p50_s": round(percentile(seq_lat, 50), 4),
         "sequential_p99_s": round(percentile(seq_lat, 99), 4),
         "max_infidelity_vs_c128": max(infid),
+        "packed_jobs": sum(1 for w in jobs if w.n_atoms <= 13),
         "precision": "c64 state, FP64 reductions, tol 1e-7",
     }
     log(f"serving: {out['served_solves_per_s']} solves/s, p50 {out['served_p50_s']} s, "
         f"p99 {out['served_p99_s']} s; max infidelity {out['max_infidelity_vs_c128']:.2e}")
+    return out
+
+
+def small_job_leg(rsv, wl, ctx, n_jobs, lanes):
+    """Saturation throughput of small jobs (N ~ U{6..13}, otherwise the serving-stream
+    recipe, complex64, tol 1e-7), all queued at t = 0: one server packs them (one workgroup
+    per job, one launch per batch), another runs each on the plain host-driven path.  Every
+    packed state is compared with the plain path's."""
+    jobs = wl.serving_stream(n_jobs, seed=2, n_min=6, n_max=13)
+    res = {}
+    for mode, pack in (("plain", 0), ("packed", 13)):
+        srv = rsv.rsv_server_create(ctx, n_lanes=lanes, arena_bytes=4 << 30, pack_max_atoms=pack)
+        try:
+            t0 = time.perf_counter()
+            for i, w in enumerate(jobs):
+                rsv.rsv_server_submit(srv, w.xyz, w.c6, rsv.PulseArrays(w.omega, w.delta),
+                                      rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12), "c64",
+                                      return_state=True, tag=i)
+            done = []
+            while len(done) < len(jobs):
+                done += rsv.rsv_server_poll(srv, 256, 1000)
+            span = time.perf_counter() - t0
+        finally:
+            rsv.rsv_server_destroy(srv)
+        bad = [c for c in done if c["status"] != 0]
+        assert not bad, bad[0]["error"]
+        res[mode] = ({c["tag"]: c["state"] for c in done}, span)
+    infid = []
+    for i in range(len(jobs)):
+        a, b = res["plain"][0][i], res["packed"][0][i]
+        a = a / np.linalg.norm(a)
+        b = b / np.linalg.norm(b)
+        r = b - np.vdot(a, b) * a
+        infid.append(float(np.vdot(r, r).real))
+    out = {"jobs": len(jobs), "n_atoms": "6..13", "lanes": lanes,
+           "plain_solves_per_s": round(len(jobs) / res["plain"][1], 2),
+           "packed_solves_per_s": round(len(jobs) / res["packed"][1], 2),
+           "max_infidelity_packed_vs_plain": max(infid)}
+    log(f"small jobs: plain {out['plain_solves_per_s']} solves/s, packed "
+        f"{out['packed_solves_per_s']} solves/s, max infidelity {max(infid):.2e}")
     return out
 
 
@@ -302,6 +343,7 @@ def main():
     torch.cuda.empty_cache()
     if args.serve_jobs > 0:
         out["serving"] = serving_leg(rsv, wl, ctx, args.serve_jobs, args.lanes)
+        out["serving"]["small_jobs"] = small_job_leg(rsv, wl, ctx, 4 * args.serve_jobs, args.lanes)
     rsv.rsv_ctx_destroy(ctx)
 
     if not args.no_cpu:

@@ -166,11 +166,21 @@ int rsv_sample_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void*
  * kmax + 3 vectors, the diagonal, the state and output scratch) fits in the server's
  * arena, first fit in arrival order.  The arena is allocated once at creation, so serving
  * never allocates or frees device memory.  A job's result does not depend on what else
- * runs: every reduction has a fixed order. */
+ * runs: every reduction has a fixed order.
+ *
+ * Small jobs (n_atoms <= pack_max_atoms, at most 12 for RSV_C128 and 13 for RSV_C64) are
+ * packed: a free lane takes the queued small jobs of the first one's precision (up to
+ * pack_max_jobs) and runs them in ONE launch, one workgroup per job, each workgroup carrying
+ * its job's whole evolution with the state on chip.  The method is that of Sec. III.A with
+ * the small exponential evaluated on the device (a Chebyshev expansion), so a packed result
+ * agrees with the plain path to the tolerance, not bit for bit; it is still independent of
+ * the batch it ran in. */
 typedef struct {
   int n_lanes;        /* concurrent jobs, 1..16 */
   size_t arena_bytes; /* device memory reserved for jobs; 0 = three quarters of free memory */
   int max_queue;      /* queued jobs beyond this make rsv_server_submit return RSV_EBUSY; 0 = no limit */
+  int pack_max_atoms; /* 0 = never pack; else jobs with n_atoms <= this (<= 13) run packed */
+  int pack_max_jobs;  /* jobs per packed launch, 0 = 256 */
 } rsv_server_opts;
 
 typedef struct {

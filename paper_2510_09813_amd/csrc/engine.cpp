@@ -231,16 +231,10 @@ int check_opts(const rsv_evolve_opts* o, const rsv_pulses* pl, int64_t* first, i
 }
 
 // ------------------------------------------------------------------------------ register
-int register_create(rsv_ctx* ctx, Allocator* alloc, int n, const double* xyz, double c6,
-                    int prec, hipStream_t stream, double* h_scal, rsv_register** out) {
-  *out = nullptr;
-  if (!ctx || !xyz) return fail(RSV_EINVAL, "NULL argument");
-  RSV_TRY(check_state_args(n, prec));
+int build_interactions(int n, const double* xyz, double c6, double* ub) {
   if (!std::isfinite(c6)) return fail(RSV_EINVAL, "C6 not finite");
   if (!finite_all(xyz, (size_t)3 * n)) return fail(RSV_EINVAL, "positions not finite");
-  // U_ij = C / |r_i - r_j|^6 (eq. 3), stored by bit position p = n-1-i
-  double ub[32 * 32];
-  std::memset(ub, 0, sizeof ub);
+  std::memset(ub, 0, 32 * 32 * sizeof(double));
   for (int i = 0; i < n; ++i) {
     for (int j = 0; j < i; ++j) {
       const double dx = xyz[3 * i] - xyz[3 * j], dy = xyz[3 * i + 1] - xyz[3 * j + 1],
@@ -252,6 +246,16 @@ int register_create(rsv_ctx* ctx, Allocator* alloc, int n, const double* xyz, do
       ub[p * 32 + q] = ub[q * 32 + p] = u;
     }
   }
+  return RSV_OK;
+}
+
+int register_create(rsv_ctx* ctx, Allocator* alloc, int n, const double* xyz, double c6,
+                    int prec, hipStream_t stream, double* h_scal, rsv_register** out) {
+  *out = nullptr;
+  if (!ctx || !xyz) return fail(RSV_EINVAL, "NULL argument");
+  RSV_TRY(check_state_args(n, prec));
+  double ub[32 * 32];
+  RSV_TRY(build_interactions(n, xyz, c6, ub));
   HIP_TRY(hipSetDevice(ctx->device));
   rsv_register* r = new (std::nothrow) rsv_register();
   if (!r) return fail(RSV_ENOMEM, "host allocation failed");

@@ -128,6 +128,10 @@ struct rsv_result {
 
 namespace rsv {
 
+// U_ij = C / |r_i - r_j|^6 (eq. 3) by bit position p = n-1-i into ub[32 * 32];
+// RSV_EINVAL for coincident atoms or non-finite input.
+int build_interactions(int n, const double* xyz, double c6, double* ub);
+
 // Builds U and the device diagonal on `stream`; memory from `alloc`; h_scal (>= 512 doubles
 // of pinned memory) is borrowed when given, else allocated.
 int register_create(rsv_ctx* ctx, Allocator* alloc, int n, const double* xyz, double c6,

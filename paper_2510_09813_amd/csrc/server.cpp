@@ -7,11 +7,17 @@
 // round trip of one job's Lanczos iteration is hidden behind the others' kernels.  Each
 // job's memory is one arena block split by a bump allocator, so admission is exactly
 // "the footprint fits" and nothing is allocated or freed on the device while serving.
+//
+// Small jobs are packed: a lane takes every queued small job of one precision (up to the
+// batch limit and its pinned staging size) as one arena block, uploads all their inputs
+// with one copy, builds each diagonal, runs them in one launch of the packed kernel (one
+// workgroup per job) and downloads all outputs with one copy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -21,6 +27,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "packed.h"
 
 using namespace rsv;
 
@@ -57,9 +64,16 @@ size_t job_bytes(int n, int kmax, int prec, int shots) {
          granule(sample_scratch_bytes(n, shots > 0 ? shots : 0)) + 4 * kGranule;
 }
 
+constexpr size_t kPackStage = size_t(32) << 20;  // pinned staging per lane, each direction
+constexpr int kPackDefaultJobs = 256;
+constexpr int kPackOutDoubles = 64;
+
 struct Job {
   uint64_t id = 0, tag = 0;
   int n = 0, prec = 0, shots = 0, return_state = 0;
+  int64_t first_step = 0, n_steps = 0;
+  bool packed = false, taken = false;
+  size_t up = 0, down = 0, work = 0;  // packed footprint: uploaded, downloaded, device-only
   double c6 = 0;
   uint64_t seed = 0;
   std::vector<double> xyz, omega, delta, phi;
@@ -161,62 +175,6 @@ int run_job(rsv_server* srv, Job* job, hipStream_t stream, double* h_pinned, rsv
   return RSV_OK;
 }
 
-Job* take_job(rsv_server* srv, std::unique_lock<std::mutex>& lk) {
-  for (;;) {
-    if (srv->stop) return nullptr;
-    for (auto it = srv->queue.begin(); it != srv->queue.end(); ++it) {
-      Job* j = *it;
-      void* block = nullptr;
-      if (srv->arena.alloc(j->bytes, &block) == RSV_OK) {
-        j->block = block;
-        srv->queue.erase(it);
-        ++srv->running;
-        return j;
-      }
-    }
-    srv->cv_work.wait(lk);
-  }
-}
-
-void lane_main(rsv_server* srv) {
-  (void)hipSetDevice(srv->ctx->device);
-  hipStream_t stream = nullptr;
-  double* h_pinned = nullptr;
-  const bool ok = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess &&
-                  hipHostMalloc((void**)&h_pinned, 512 * sizeof(double), hipHostMallocDefault) ==
-                      hipSuccess;
-  for (;;) {
-    Job* job = nullptr;
-    {
-      std::unique_lock<std::mutex> lk(srv->mu);
-      job = take_job(srv, lk);
-    }
-    if (!job) break;
-    rsv_completion c;
-    std::memset(&c, 0, sizeof c);
-    c.job_id = job->id;
-    c.tag = job->tag;
-    c.n_atoms = job->n;
-    c.t_submit = job->t_submit;
-    c.t_start = srv->now();
-    const int rc = ok ? run_job(srv, job, stream, h_pinned, c)
-                      : fail(RSV_EDEVICE, "lane could not create its stream");
-    c.t_end = srv->now();
-    fill_error(c, rc);
-    srv->arena.release(job->block, job->bytes);
-    delete job;
-    {
-      std::lock_guard<std::mutex> lk(srv->mu);
-      --srv->running;
-      srv->done.push_back(c);
-    }
-    srv->cv_done.notify_all();
-    srv->cv_work.notify_all();  // memory was released: queued jobs may fit now
-  }
-  if (stream) (void)hipStreamDestroy(stream);
-  if (h_pinned) (void)hipHostFree(h_pinned);
-}
-
 void free_completion(rsv_completion& c) {
   delete[] c.occupations;
   delete[] c.samples;
@@ -224,6 +182,343 @@ void free_completion(rsv_completion& c) {
   c.occupations = nullptr;
   c.samples = nullptr;
   c.state = nullptr;
+}
+
+// ---------------------------------------------------------------------- packed batches
+
+size_t pulse_count(const Job& j) {
+  return (size_t)j.pulses.n_samples * (j.pulses.per_site ? (size_t)j.n : 1);
+}
+
+// Footprint of a packed job: uploaded (U, pulses, initial state), downloaded (status and
+// occupations, samples, final state) and device-only (diagonal, state, Krylov basis,
+// sampling scratch).
+void packed_sizes(Job& j) {
+  const size_t dim = size_t(1) << j.n, cnt = pulse_count(j);
+  j.up = granule(32 * 32 * 8) + 2 * granule(cnt * 8) + (j.phi.empty() ? 0 : granule(cnt * 8)) +
+         (j.psi0.empty() ? 0 : granule(dim * 16));
+  j.down = granule(kPackOutDoubles * 8) + granule((size_t)j.shots * 8) +
+           (j.return_state ? granule(dim * 16) : 0);
+  j.work = granule(dim * (j.prec == kC128 ? 8 : 4)) + granule(vec_bytes(j.n, j.prec)) +
+           granule((size_t)j.opts.kmax * vec_bytes(j.n, j.prec)) +
+           (j.shots > 0 ? granule((size_t)sample_scratch_doubles(j.n) * 8) : 0);
+}
+
+size_t batch_bytes(size_t count, size_t up, size_t down, size_t work) {
+  return granule(count * sizeof(PackedJob)) + up + down + work;
+}
+
+struct Work {
+  std::vector<Job*> jobs;  // one plain job, or a packed batch
+  bool packed = false;
+  void* block = nullptr;
+  size_t bytes = 0;
+};
+
+// Packed batch starting at queue position `first`: that job and the later packed jobs of
+// its precision, in arrival order, within the batch limit and the staging size; shrunk
+// from the end until its block fits the arena.
+bool take_batch(rsv_server* srv, size_t first, Work& w) {
+  const Job* lead = srv->queue[first];
+  const size_t max_jobs = srv->opts.pack_max_jobs > 0 ? srv->opts.pack_max_jobs : kPackDefaultJobs;
+  std::vector<Job*> cand;
+  std::vector<size_t> up{0}, down{0}, work{0};  // prefix sums
+  for (size_t q = first; q < srv->queue.size() && cand.size() < max_jobs; ++q) {
+    Job* j = srv->queue[q];
+    if (!j->packed || j->prec != lead->prec) continue;
+    const size_t u = up.back() + j->up, d = down.back() + j->down;
+    if (granule((cand.size() + 1) * sizeof(PackedJob)) + u > kPackStage || d > kPackStage) break;
+    cand.push_back(j);
+    up.push_back(u);
+    down.push_back(d);
+    work.push_back(work.back() + j->work);
+  }
+  for (size_t k = cand.size(); k >= 1; k = k / 2) {
+    const size_t bytes = batch_bytes(k, up[k], down[k], work[k]);
+    void* block = nullptr;
+    if (srv->arena.alloc(bytes, &block) == RSV_OK) {
+      w.jobs.assign(cand.begin(), cand.begin() + k);
+      w.packed = true;
+      w.block = block;
+      w.bytes = bytes;
+      return true;
+    }
+  }
+  return false;
+}
+
+// First queued work (arrival order) whose memory fits: a plain job, or a packed batch led
+// by the first packed job that fits.
+bool take_work(rsv_server* srv, std::unique_lock<std::mutex>& lk, Work& w) {
+  for (;;) {
+    if (srv->stop) return false;
+    for (size_t q = 0; q < srv->queue.size(); ++q) {
+      Job* j = srv->queue[q];
+      bool got = false;
+      if (j->packed) {
+        got = take_batch(srv, q, w);
+      } else {
+        void* block = nullptr;
+        if (srv->arena.alloc(j->bytes, &block) == RSV_OK) {
+          j->block = block;
+          w.jobs.assign(1, j);
+          w.packed = false;
+          w.block = block;
+          w.bytes = j->bytes;
+          got = true;
+        }
+      }
+      if (got) {
+        for (Job* t : w.jobs) t->taken = true;
+        srv->queue.erase(std::remove_if(srv->queue.begin(), srv->queue.end(),
+                                        [](Job* x) { return x->taken; }),
+                         srv->queue.end());
+        srv->running += (int)w.jobs.size();
+        return true;
+      }
+    }
+    srv->cv_work.wait(lk);
+  }
+}
+
+struct LaneBuffers {
+  hipStream_t stream = nullptr;
+  double* h_pinned = nullptr;  // 512 doubles of per-iteration scalars
+  char* h_up = nullptr;        // packed staging, kPackStage bytes each
+  char* h_down = nullptr;
+};
+
+// Device and staging addresses of one packed job inside its batch block.
+struct PackedSlot {
+  size_t up_off, down_off;  // offsets within the upload / download regions
+  double *ub, *omega, *delta, *phi;
+  void* psi0;  // complex128 initial state or null
+  double* out;
+  uint64_t* idx;
+  void* state;  // complex128 final state or null
+  void *diag, *psi, *basis;
+  double* scratch;
+  int status;  // RSV_OK, or an input error found on the host
+};
+
+// Runs a packed batch: one upload, per-job diagonal builds, one packed launch, per-job
+// samples and state exports, one download.  Completions are appended to `out`.
+int run_batch(rsv_server* srv, Work& w, LaneBuffers& lb, std::vector<rsv_completion>& out,
+              double t_start) {
+  const size_t count = w.jobs.size();
+  const int prec = w.jobs[0]->prec;
+  hipStream_t s = lb.stream;
+  size_t up_total = granule(count * sizeof(PackedJob)), down_total = 0, work_total = 0;
+  for (Job* j : w.jobs) {
+    up_total += j->up;
+    down_total += j->down;
+    work_total += j->work;
+  }
+  char* up_base = (char*)w.block;  // [descriptors | per-job inputs]
+  char* down_base = up_base + up_total;
+  char* work_base = down_base + down_total;
+  std::vector<PackedSlot> slot(count);
+  PackedJob* desc = (PackedJob*)lb.h_up;
+  size_t uo = granule(count * sizeof(PackedJob)), dw = 0, wo = 0;
+  int launched = 0;
+  for (size_t i = 0; i < count; ++i) {
+    Job* j = w.jobs[i];
+    PackedSlot& sl = slot[i];
+    const size_t dim = size_t(1) << j->n, cnt = pulse_count(*j);
+    auto take_up = [&](size_t bytes, const void* src) {
+      std::memcpy(lb.h_up + uo, src, bytes);
+      void* dev = up_base + uo;
+      uo += granule(bytes);
+      return dev;
+    };
+    sl.up_off = uo;
+    sl.status = build_interactions(j->n, j->xyz.data(), j->c6, (double*)(lb.h_up + uo));
+    sl.ub = (double*)(up_base + uo);
+    uo += granule(32 * 32 * 8);
+    sl.omega = (double*)take_up(cnt * 8, j->omega.data());
+    sl.delta = (double*)take_up(cnt * 8, j->delta.data());
+    sl.phi = j->phi.empty() ? nullptr : (double*)take_up(cnt * 8, j->phi.data());
+    sl.psi0 = j->psi0.empty() ? nullptr : take_up(dim * 16, j->psi0.data());
+    sl.down_off = dw;
+    sl.out = (double*)(down_base + dw);
+    dw += granule(kPackOutDoubles * 8);
+    sl.idx = (uint64_t*)(down_base + dw);
+    dw += granule((size_t)j->shots * 8);
+    sl.state = j->return_state ? down_base + dw : nullptr;
+    dw += j->return_state ? granule(dim * 16) : 0;
+    sl.diag = work_base + wo;
+    wo += granule(dim * (prec == kC128 ? 8 : 4));
+    sl.psi = work_base + wo;
+    wo += granule(vec_bytes(j->n, prec));
+    sl.basis = work_base + wo;
+    wo += granule((size_t)j->opts.kmax * vec_bytes(j->n, prec));
+    sl.scratch = (double*)(work_base + wo);
+    wo += j->shots > 0 ? granule((size_t)sample_scratch_doubles(j->n) * 8) : 0;
+    if (sl.status != RSV_OK) continue;
+    PackedJob& d = desc[launched++];
+    d.n = j->n;
+    d.dt_ns = j->opts.dt_ns;
+    d.kmax = j->opts.kmax;
+    d.max_depth = j->opts.max_substep_depth;
+    d.per_site = j->pulses.per_site;
+    d.init_zero = j->psi0.empty() ? 1 : 0;
+    d.first_step = j->first_step;
+    d.n_steps = j->n_steps;
+    d.n_samples = j->pulses.n_samples;
+    d.tol = j->opts.tol;
+    d.omega = sl.omega;
+    d.delta = sl.delta;
+    d.phi = sl.phi;
+    d.diag = sl.diag;
+    d.psi = sl.psi;
+    d.basis = sl.basis;
+    d.out = sl.out;
+  }
+  HIP_TRY(hipMemcpyAsync(up_base, lb.h_up, up_total, hipMemcpyHostToDevice, s));
+  for (size_t i = 0; i < count; ++i) {
+    const PackedSlot& sl = slot[i];
+    const Job* j = w.jobs[i];
+    if (sl.status != RSV_OK) continue;
+    HIP_TRY(diag_build(prec, j->n, sl.ub, sl.diag, s));
+    if (sl.psi0) {
+      if (prec == kC128)
+        HIP_TRY(hipMemcpyAsync(sl.psi, sl.psi0, (size_t(1) << j->n) * 16, hipMemcpyDeviceToDevice, s));
+      else
+        HIP_TRY(convert_from_c128(prec, j->n, sl.psi0, sl.psi, s));
+    }
+  }
+  HIP_TRY(packed_evolve(prec, (const PackedJob*)up_base, launched, s));
+  for (size_t i = 0; i < count; ++i) {
+    const PackedSlot& sl = slot[i];
+    const Job* j = w.jobs[i];
+    if (sl.status != RSV_OK) continue;
+    if (j->shots > 0) HIP_TRY(sample(prec, j->n, sl.psi, j->seed, j->shots, sl.scratch, sl.idx, s));
+    if (sl.state) {
+      if (prec == kC128)
+        HIP_TRY(hipMemcpyAsync(sl.state, sl.psi, (size_t(1) << j->n) * 16, hipMemcpyDeviceToDevice, s));
+      else
+        HIP_TRY(convert_to_c128(prec, j->n, sl.psi, sl.state, s));
+    }
+  }
+  if (down_total) HIP_TRY(hipMemcpyAsync(lb.h_down, down_base, down_total, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double t_end = srv->now();
+  for (size_t i = 0; i < count; ++i) {
+    const PackedSlot& sl = slot[i];
+    Job* j = w.jobs[i];
+    rsv_completion c;
+    std::memset(&c, 0, sizeof c);
+    c.job_id = j->id;
+    c.tag = j->tag;
+    c.n_atoms = j->n;
+    c.t_submit = j->t_submit;
+    c.t_start = t_start;
+    c.t_end = t_end;
+    int status = sl.status;
+    const double* o = (const double*)(lb.h_down + sl.down_off);
+    if (status == RSV_OK) {
+      status = (int)o[0];
+      if (status == RSV_ENOTCONV)
+        fail(status, "Krylov estimate above tolerance at the deepest sub-step");
+      else if (status != RSV_OK)
+        fail(status, "non-finite Lanczos coefficients or zero state");
+      else if (!(o[4] > 0.0))
+        status = fail(RSV_ENUMERIC, "state has zero norm");
+    }
+    if (status == RSV_OK) {
+      const int n = j->n;
+      c.stats.steps = j->n_steps;
+      c.stats.krylov_iters = (int64_t)o[1];
+      c.stats.krylov_max = (int64_t)o[2];
+      c.stats.substeps = (int64_t)o[3];
+      c.stats.norm_final = std::sqrt(o[4]);
+      c.stats.seconds = t_end - t_start;
+      c.occupations = new double[n];
+      for (int a = 0; a < n; ++a) c.occupations[a] = o[kPackOccOffset + (n - 1 - a)] / o[4];
+      if (j->shots > 0) {
+        c.n_shots = j->shots;
+        c.samples = new uint64_t[j->shots];
+        std::memcpy(c.samples, lb.h_down + sl.down_off + granule(kPackOutDoubles * 8),
+                    (size_t)j->shots * 8);
+      }
+      if (j->return_state) {
+        const size_t b = (size_t(1) << n) * 16;
+        c.state = new double[(size_t(1) << n) * 2];
+        std::memcpy(c.state, (char*)sl.state - down_base + lb.h_down, b);
+      }
+    }
+    fill_error(c, status);
+    out.push_back(c);
+  }
+  return RSV_OK;
+}
+
+void lane_main(rsv_server* srv) {
+  (void)hipSetDevice(srv->ctx->device);
+  LaneBuffers lb;
+  bool ok = hipStreamCreateWithFlags(&lb.stream, hipStreamNonBlocking) == hipSuccess &&
+            hipHostMalloc((void**)&lb.h_pinned, 512 * sizeof(double), hipHostMallocDefault) ==
+                hipSuccess;
+  if (ok && srv->opts.pack_max_atoms > 0)
+    ok = hipHostMalloc((void**)&lb.h_up, kPackStage, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc((void**)&lb.h_down, kPackStage, hipHostMallocDefault) == hipSuccess;
+  for (;;) {
+    Work w;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      if (!take_work(srv, lk, w)) break;
+    }
+    std::vector<rsv_completion> comps;
+    const double t_start = srv->now();
+    if (w.packed) {
+      const int rc = ok ? run_batch(srv, w, lb, comps, t_start)
+                        : fail(RSV_EDEVICE, "lane could not allocate its buffers");
+      if (rc != RSV_OK) {  // a device error ends the whole batch
+        for (rsv_completion& c : comps) free_completion(c);
+        comps.clear();
+        const double t_end = srv->now();
+        for (Job* j : w.jobs) {
+          rsv_completion c;
+          std::memset(&c, 0, sizeof c);
+          c.job_id = j->id;
+          c.tag = j->tag;
+          c.n_atoms = j->n;
+          c.t_submit = j->t_submit;
+          c.t_start = t_start;
+          c.t_end = t_end;
+          fill_error(c, rc);
+          comps.push_back(c);
+        }
+      }
+    } else {
+      Job* job = w.jobs[0];
+      rsv_completion c;
+      std::memset(&c, 0, sizeof c);
+      c.job_id = job->id;
+      c.tag = job->tag;
+      c.n_atoms = job->n;
+      c.t_submit = job->t_submit;
+      c.t_start = t_start;
+      const int rc = ok ? run_job(srv, job, lb.stream, lb.h_pinned, c)
+                        : fail(RSV_EDEVICE, "lane could not allocate its buffers");
+      c.t_end = srv->now();
+      fill_error(c, rc);
+      comps.push_back(c);
+    }
+    srv->arena.release(w.block, w.bytes);
+    for (Job* j : w.jobs) delete j;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->running -= (int)w.jobs.size();
+      for (rsv_completion& c : comps) srv->done.push_back(c);
+    }
+    srv->cv_done.notify_all();
+    srv->cv_work.notify_all();  // memory was released: queued jobs may fit now
+  }
+  if (lb.stream) (void)hipStreamDestroy(lb.stream);
+  if (lb.h_pinned) (void)hipHostFree(lb.h_pinned);
+  if (lb.h_up) (void)hipHostFree(lb.h_up);
+  if (lb.h_down) (void)hipHostFree(lb.h_down);
 }
 
 }  // namespace
@@ -241,6 +536,9 @@ int rsv_server_create(rsv_ctx* ctx, const rsv_server_opts* opts, rsv_server** ou
   if (!ctx || !opts) return fail(RSV_EINVAL, "NULL argument");
   if (opts->n_lanes < 1 || opts->n_lanes > 16) return fail(RSV_EINVAL, "n_lanes must be in 1..16");
   if (opts->max_queue < 0) return fail(RSV_EINVAL, "max_queue must be >= 0");
+  if (opts->pack_max_atoms < 0 || opts->pack_max_atoms > kMaxPackBits)
+    return fail(RSV_EINVAL, "pack_max_atoms must be in 0..%d", kMaxPackBits);
+  if (opts->pack_max_jobs < 0) return fail(RSV_EINVAL, "pack_max_jobs must be >= 0");
   HIP_TRY(hipSetDevice(ctx->device));
   size_t bytes = opts->arena_bytes;
   if (bytes == 0) {
@@ -291,7 +589,16 @@ int rsv_server_submit(rsv_server* srv, const rsv_job_desc* jd, uint64_t* job_id)
     const double* p = (const double*)jd->psi0_host;
     j->psi0.assign(p, p + (size_t(2) << n));
   }
-  j->bytes = job_bytes(n, jd->opts.kmax, jd->prec, jd->n_shots);
+  j->first_step = first;
+  j->n_steps = count;
+  j->packed = n <= std::min(srv->opts.pack_max_atoms, packed_max_atoms(jd->prec));
+  if (j->packed) {
+    packed_sizes(*j);
+    // too large for one staging buffer: the plain path takes it
+    j->packed = granule(sizeof(PackedJob)) + j->up <= kPackStage && j->down <= kPackStage;
+  }
+  j->bytes = j->packed ? batch_bytes(1, j->up, j->down, j->work)
+                       : job_bytes(n, jd->opts.kmax, jd->prec, jd->n_shots);
   if (j->bytes > srv->arena.capacity())
     return fail(RSV_ENOMEM, "job needs %zu bytes, the arena holds %zu", j->bytes,
                 srv->arena.capacity());

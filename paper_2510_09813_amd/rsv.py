@@ -276,7 +276,8 @@ def rsv_tridiag_expm(alpha, beta, tau: float):
 
 # ------------------------------------------------------------------------- serving
 class ServerOpts(C.Structure):
-    _fields_ = [("n_lanes", C.c_int), ("arena_bytes", C.c_size_t), ("max_queue", C.c_int)]
+    _fields_ = [("n_lanes", C.c_int), ("arena_bytes", C.c_size_t), ("max_queue", C.c_int),
+                ("pack_max_atoms", C.c_int), ("pack_max_jobs", C.c_int)]
 
 
 class JobDesc(C.Structure):
@@ -326,9 +327,10 @@ def _slib():
     return L
 
 
-def rsv_server_create(ctx, n_lanes: int = 4, arena_bytes: int = 0, max_queue: int = 0):
+def rsv_server_create(ctx, n_lanes: int = 4, arena_bytes: int = 0, max_queue: int = 0,
+                      pack_max_atoms: int = 0, pack_max_jobs: int = 0):
     h = C.c_void_p()
-    opts = ServerOpts(n_lanes, arena_bytes, max_queue)
+    opts = ServerOpts(n_lanes, arena_bytes, max_queue, pack_max_atoms, pack_max_jobs)
     _check(_slib().rsv_server_create(ctx, C.byref(opts), C.byref(h)))
     return h
 

@@ -149,3 +149,130 @@ def test_rejections_and_cancel(ctx):
             rsv.rsv_server_cancel(srv, 123456)
     finally:
         rsv.rsv_server_destroy(srv)
+
+
+# ---------------------------------------------------------------------- packed small jobs
+PACK = {"c128": 12, "c64": 13}
+FID = {"c128": 1e-9, "c64": 2e-5}
+
+
+def packed_cases(prec):
+    """Small jobs for the packed launch: 1 atom (an invariant subspace at the second Lanczos
+    vector), 2 atoms, up to the largest packed size, a per-site drive with a phase and
+    dt = 5 ns, and a random initial state."""
+    rng = np.random.default_rng(21)
+    out = []
+    for n in (1, 2, 6, 9, 10, 11, PACK[prec]):
+        w = wl.serving_job(rng, n_min=n, n_max=n, precision=prec)
+        t = min(w.t_ns, 500)
+        w.t_ns, w.omega, w.delta = t, w.omega[:t + 1], w.delta[:t + 1]
+        out.append((w, None))
+    n, t = 7, 300
+    w = wl.serving_job(rng, n_min=n, n_max=n, dt_ns=5, precision=prec)
+    ts = np.arange(t + 1) / t
+    w.t_ns = t
+    w.omega = np.stack([(1.0 + 0.2 * i) * 6.0 * np.sin(np.pi * ts) for i in range(n)])
+    w.delta = np.stack([(-8.0 + 3.0 * i) * (1.0 - 2.0 * ts) for i in range(n)])
+    w.phi = np.stack([0.3 * i + 1.5 * ts for i in range(n)])
+    out.append((w, None))
+    w = wl.serving_job(rng, n_min=8, n_max=8, precision=prec)
+    w.t_ns, w.omega, w.delta = 400, w.omega[:401], w.delta[:401]
+    out.append((w, wl.random_state(8, rng)))
+    return out
+
+
+def reference(w, psi0):
+    method = "dense" if w.n_atoms <= 10 else "lanczos"
+    return evolve.evolve_workload(w, method=method, psi0=psi0)
+
+
+def submit_case(srv, w, psi0, prec, tag, shots=500, seed=17):
+    return rsv.rsv_server_submit(srv, w.xyz, w.c6, rsv.PulseArrays(w.omega, w.delta, w.phi),
+                                 rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12), prec, psi0=psi0,
+                                 n_shots=shots, seed=seed, return_state=True, tag=tag)
+
+
+def serve(ctx, cases, prec, pack, lanes=1, **kw):
+    srv = rsv.rsv_server_create(ctx, n_lanes=lanes, arena_bytes=1 << 30,
+                                pack_max_atoms=PACK[prec] if pack else 0, **kw)
+    try:
+        for i, (w, p0) in enumerate(cases):
+            submit_case(srv, w, p0, prec, tag=i)
+        done = drain(srv, len(cases))
+    finally:
+        rsv.rsv_server_destroy(srv)
+    return {c["tag"]: c for c in done}
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_packed_matches_oracle_and_plain_path(ctx, prec):
+    cases = packed_cases(prec)
+    packed = serve(ctx, cases, prec, pack=True)
+    plain = serve(ctx, cases, prec, pack=False, lanes=2)
+    for i, (w, p0) in enumerate(cases):
+        c, h = packed[i], plain[i]
+        assert c["status"] == rsv.RSV_OK, (w.n_atoms, c["error"])
+        assert h["status"] == rsv.RSV_OK, (w.n_atoms, h["error"])
+        ref = reference(w, p0)
+        assert observables.fidelity_loss(ref, c["state"]) <= FID[prec], (i, w.n_atoms)
+        assert observables.fidelity_loss(h["state"], c["state"]) <= FID[prec], (i, w.n_atoms)
+        # outputs of the packed path are those of its own final state
+        np.testing.assert_allclose(c["occupations"], observables.occupations(c["state"]),
+                                   atol=1e-12)
+        want = observables.sample(c["state"], 17, 500)
+        assert np.count_nonzero(c["samples"] == want) >= 498
+        st = c["stats"]
+        assert st["steps"] == w.n_steps and st["krylov_iters"] >= w.n_steps
+        assert 1 <= st["krylov_max"] <= w.kmax
+        assert abs(st["norm_final"] - np.linalg.norm(p0 if p0 is not None else [1.0])) <= (
+            1e-10 if prec == "c128" else 1e-5)
+    # one atom: the Krylov space closes at dimension 2 (complex64 rounding may leave a third
+    # vector of rounding noise before the estimate drops below the tolerance)
+    assert packed[0]["stats"]["krylov_max"] <= (2 if prec == "c128" else 3)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_packed_alone_equals_in_batch(ctx, prec):
+    """A packed job's result is the same, bit for bit, alone and inside a batch."""
+    cases = packed_cases(prec)
+    together = serve(ctx, cases, prec, pack=True)
+    starts = [c["t_start"] for c in together.values()]
+    assert len(set(starts)) < len(starts), "no two jobs shared a launch"
+    for i, case in enumerate(cases):
+        alone_c = serve(ctx, [case], prec, pack=True)[0]
+        c = together[i]
+        assert np.array_equal(alone_c["state"], c["state"])
+        assert np.array_equal(alone_c["occupations"], c["occupations"])
+        assert np.array_equal(alone_c["samples"], c["samples"])
+
+
+def test_packed_strong_interactions_and_errors(ctx):
+    """Atoms 2 um apart make exp(-i dt T) too wide for one Chebyshev series: the packed
+    path sub-steps and still matches the oracle; a job that cannot converge fails alone."""
+    w = wl.serving_job(np.random.default_rng(4), n_min=4, n_max=4, precision="c128")
+    w.xyz = wl.chain(4, 2.0)
+    w.t_ns, w.omega, w.delta = 100, w.omega[:101], w.delta[:101]
+    bad = wl.serving_job(np.random.default_rng(5), n_min=9, n_max=9, precision="c128")
+    srv = rsv.rsv_server_create(ctx, n_lanes=1, arena_bytes=256 << 20, pack_max_atoms=12)
+    try:
+        submit_case(srv, w, None, "c128", tag=0)
+        rsv.rsv_server_submit(srv, bad.xyz, bad.c6, rsv.PulseArrays(bad.omega, bad.delta),
+                              rsv.evolve_opts(bad.dt_ns, 1e-14, 2, 1), "c128", tag=1)
+        submit_case(srv, w, None, "c128", tag=2)
+        done = {c["tag"]: c for c in drain(srv, 3)}
+    finally:
+        rsv.rsv_server_destroy(srv)
+    assert done[1]["status"] == rsv.RSV_ENOTCONV
+    for t in (0, 2):
+        assert done[t]["status"] == rsv.RSV_OK, done[t]["error"]
+        assert done[t]["stats"]["substeps"] > 0
+        ref = evolve.evolve_workload(w, method="dense")
+        assert observables.fidelity_loss(ref, done[t]["state"]) <= 1e-9
+    assert np.array_equal(done[0]["state"], done[2]["state"])
+
+
+def test_packed_options_rejected(ctx):
+    for kw in ({"pack_max_atoms": 14}, {"pack_max_atoms": -1}, {"pack_max_jobs": -3}):
+        with pytest.raises(rsv.RsvError) as e:
+            rsv.rsv_server_create(ctx, n_lanes=1, arena_bytes=1 << 20, **kw)
+        assert e.value.code == rsv.RSV_EINVAL
