@@ -36,10 +36,12 @@ __device__ __forceinline__ double block_sum_256(double v, double* red /* >= 4 do
   return r;
 }
 
-// acc + (x^2 + y^2) with every product and sum rounded separately (no FMA contraction), so
-// that every kernel that accumulates a squared norm of the same values gets the same bits.
+// acc + (x^2 + y^2) with every product and sum rounded separately, so that every kernel
+// that accumulates a squared norm of the same values gets the same bits.  The pragma keeps
+// the operations out of FMA contraction after inlining (the _rn intrinsics alone do not).
 __device__ __forceinline__ double norm_add(double acc, double x, double y) {
-  return __dadd_rn(acc, __dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)));
+#pragma clang fp contract(off)
+  return acc + (x * x + y * y);
 }
 
 // Fixed grid for the streaming vector kernels: 8 workgroups per CU on 256 CUs at most.

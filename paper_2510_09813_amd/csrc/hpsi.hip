@@ -32,7 +32,8 @@ namespace rsv {
 namespace {
 
 // Tile geometry per storage precision: low-pass tile bits L and threads NL; high-pass tile
-// bits H, contiguous run bits RL (RLW for a narrow last pass) and threads NH.
+// bits H and threads NH, with a contiguous run of RL..RLW bits per pass (longer runs stream
+// better; the planner gives each pass the longest run the bit count allows).
 template <class R> struct Geo;
 template <> struct Geo<double> {
   static constexpr int L = 12, NL = 1024, H = 12, RL = 3, RLW = 6, NH = 1024;
@@ -40,6 +41,9 @@ template <> struct Geo<double> {
 template <> struct Geo<float> {
   static constexpr int L = 13, NL = 1024, H = 12, RL = 3, RLW = 6, NH = 1024;
 };
+static_assert(Geo<double>::RL == 3 && Geo<double>::RLW == 6 && Geo<float>::RL == 3 &&
+                  Geo<float>::RLW == 6,
+              "launch_hi instantiates run lengths 3..6");
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
 
@@ -193,14 +197,20 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
   if (CM == kCoefSite) build_delta_lut<R>(c, lut);
 
   const double b1 = input_coef1(p);
-  C v[A];
+  C v[A], tv[A];
+  R dg[A];
   double nrm = 0.0;
+  // every HBM operand is requested before the barrier, so the loads of the diagonal and of
+  // the high-pass partial overlap those of the state
 #pragma unroll
   for (int s = 0; s < A; ++s) {
     const uint32_t e = tid + NT * s;
     v[s] = form<R>(p, b1, base + e);
-    tile[e] = v[s];
+    dg[s] = p.diag[base + e];
+    tv[s] = p.tb ? p.tb[base + e] : C{0, 0};
   }
+#pragma unroll
+  for (int s = 0; s < A; ++s) tile[tid + NT * s] = v[s];
   if (p.u_out) {
 #pragma unroll
     for (int s = 0; s < A; ++s) {
@@ -215,7 +225,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
   for (int s = 0; s < A; ++s) {
     const uint32_t e = tid + NT * s;
     const uint32_t b = base + e;
-    const R d = p.diag[b] + detuning<R, CM>(c, lut, b);
+    const R d = dg[s] + detuning<R, CM>(c, lut, b);
     C acc = {d * v[s].x, d * v[s].y};
     DriveSum<R, CM> ds;
 #pragma unroll
@@ -223,7 +233,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
 #pragma unroll
     for (int q = 0; q < RB; ++q) ds.add(c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
     ds.finish(c, acc);
-    if (p.tb) cadd<R>(acc, p.tb[b]);
+    if (p.tb) cadd<R>(acc, tv[s]);
     p.out[b] = acc;
     dot += (double)v[s].x * (double)acc.x + (double)v[s].y * (double)acc.y;
   }
@@ -361,10 +371,12 @@ void launch_lo_any(int lb, const StepCoef& c, const PassArgs<R>& p, int n, hipSt
 template <class R, int CM>
 void launch_hi(int rl, const StepCoef& c, const PassArgs<R>& p, hipStream_t s) {
   constexpr int HB = Geo<R>::H, NT = Geo<R>::NH;
-  if (rl == Geo<R>::RL)
-    hipLaunchKernelGGL((hpsi_hi_kernel<R, HB, Geo<R>::RL, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p);
-  else
-    hipLaunchKernelGGL((hpsi_hi_kernel<R, HB, Geo<R>::RLW, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p);
+  switch (rl) {
+    case 3: hipLaunchKernelGGL((hpsi_hi_kernel<R, HB, 3, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p); break;
+    case 4: hipLaunchKernelGGL((hpsi_hi_kernel<R, HB, 4, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p); break;
+    case 5: hipLaunchKernelGGL((hpsi_hi_kernel<R, HB, 5, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p); break;
+    default: hipLaunchKernelGGL((hpsi_hi_kernel<R, HB, 6, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p); break;
+  }
 }
 
 template <class R, int CM>
@@ -455,20 +467,27 @@ TilePlan make_tile_plan(int prec, int n) {
   p.hi_bits = prec == kC128 ? Geo<double>::H : Geo<float>::H;
   p.lo_bits = n < L ? n : L;
   p.n_hi_passes = 0;
-  const int g = p.hi_bits - rl;
-  for (int f0 = p.lo_bits; f0 < n; f0 += g) {
-    const int f1 = f0 + g < n ? f0 + g : n;
-    // a narrow last pass takes a wider contiguous run (better coalescing), a full one the
-    // narrow run that leaves the most bits for flips
-    const int r = (f1 - f0 <= p.hi_bits - rlw && n - (p.hi_bits - rlw) >= rlw) ? rlw : rl;
+  const int rest = n - p.lo_bits;  // bits the high passes flip
+  if (rest <= 0) return p;
+  // fewest passes at the shortest run, then the spare tile bits lengthen the runs (the
+  // first, forming pass first: it moves the most bytes), up to rlw each
+  const int passes = (rest + p.hi_bits - rl - 1) / (p.hi_bits - rl);
+  int spare = passes * (p.hi_bits - rl) - rest;
+  int f0 = p.lo_bits;
+  for (int i = 0; i < passes; ++i) {
+    const int per = (spare + (passes - i) - 1) / (passes - i);  // spread, rounding up first
+    const int r = rl + per < rlw ? rl + per : rlw;
+    spare -= r - rl;
     const int gw = p.hi_bits - r;
+    const int f1 = f0 + gw < n ? f0 + gw : n;
     int a = f0;
     if (a + gw > n) a = n - gw;  // keep the whole tile inside the index; extra bits are not flipped
-    p.flip_lo[p.n_hi_passes] = f0;
-    p.flip_hi[p.n_hi_passes] = f1;
-    p.tile_a[p.n_hi_passes] = a;
-    p.run_bits[p.n_hi_passes] = r;
+    p.flip_lo[i] = f0;
+    p.flip_hi[i] = f1;
+    p.tile_a[i] = a;
+    p.run_bits[i] = r;
     ++p.n_hi_passes;
+    f0 = f1;
   }
   return p;
 }

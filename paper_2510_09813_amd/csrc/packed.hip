@@ -81,7 +81,17 @@ __device__ bool cheb_expm(Shared& sh, int m, double tau, bool full) {
     int K = -1;  // -1: T is numerically a multiple of the identity; -2: series too long
     if (r > 1e-300 && tau * r > 1e-30) {
       const double a = tau * r;
+      // terms: J_k(a) <= (a/2)^k / k! bounds the tail for small a; a + 8 a^(1/3) + 20 for
+      // large a (both leave a tail below 1e-15)
       K = (int)(a + 8.0 * cbrt(a) + 20.0);
+      double bound = 1.0;
+      for (int k = 1; k < K; ++k) {
+        bound *= 0.5 * a / k;
+        if (k > 0.5 * a + 1.0 && bound < 1e-17) {
+          K = k;
+          break;
+        }
+      }
       if (K > kMaxBessel - 1) {
         sh.cheb_k = -2;
         K = -3;
@@ -91,12 +101,13 @@ __device__ bool cheb_expm(Shared& sh, int m, double tau, bool full) {
       const double a = tau * r;
       // Miller's backward recurrence for J_0..J_K(a), normalised by J_0 + 2 sum J_2k = 1
       const int M = K + 24 + (int)sqrt(40.0 * (K + 1));
+      const double two_over_a = 2.0 / a;
       double jp = 0.0, j = 1e-280, norm = 0.0;
       for (int k = 0; k <= K; ++k) sh.bessel[k] = 0.0;
       for (int k = M; k >= 1; --k) {
         if (k <= K) sh.bessel[k] = j;
         if (!(k & 1)) norm += 2.0 * j;
-        const double jm = (2.0 * k / a) * j - jp;
+        const double jm = (k * two_over_a) * j - jp;
         jp = j;
         j = jm;
         if (fabs(j) > 1e200) {  // rescale everything recurred so far
@@ -193,6 +204,7 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
     if (mine(s)) tile[e] = jb.init_zero ? C{(R)(e == 0 ? 1 : 0), 0} : psi[e];
   }
   int64_t iters = 0, kmax_used = 0, substeps = 0;
+  int m_prev = 0;  // Krylov dimension of the previous Lanczos run of this job
   int status = RSV_OK;
   const double tau = jb.dt_ns * 1e-3;
 
@@ -276,6 +288,9 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
       // target: the part of the step this basis must resolve; shortened while the
       // exponential of the growing T_m is too wide for one Chebyshev series
       double target = remaining, sub = remaining;
+      // the estimate is first tested two dimensions below the previous run's (every
+      // dimension on the first run): a larger m than the smallest converged one is as exact
+      const int k_test = m_prev > 3 ? m_prev - 2 : 1;
       for (int k = 1; k <= jb.kmax; ++k) {
         const double sk1 = sh.scale[k - 1];
         const double alpha = sk1 * sk1 * dot;
@@ -303,39 +318,41 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
         m = k;
         // the estimate meets the tolerance (always so at beta = 0, an invariant subspace)
         auto resolved = [&]() { return bk * sh.est * nrm <= jb.tol; };
-        bool fits = cheb_expm(sh, m, target, false);
-        for (int h = 0; h < 64 && !fits; ++h) fits = cheb_expm(sh, m, target *= 0.5, false);
-        if (!fits) {
-          status = RSV_ENOTCONV;
-          break;
-        }
-        if (resolved()) {
-          sub = target;
-          break;
-        }
-        if (k == jb.kmax || bk == 0.0) {
-          // the longest part of the target this basis resolves: dyadic bracket, bisection
-          bool ok = false;
-          double bad = target;
-          for (int dd = 1; dd <= jb.max_depth && !ok; ++dd) {
-            sub = ldexp(target, -dd);
-            cheb_expm(sh, m, sub, false);
-            ok = resolved();
-            __syncthreads();
-            if (!ok) bad = sub;
-          }
-          if (!ok) {
+        if (k >= k_test || k == jb.kmax || bk == 0.0) {
+          bool fits = cheb_expm(sh, m, target, false);
+          for (int h = 0; h < 64 && !fits; ++h) fits = cheb_expm(sh, m, target *= 0.5, false);
+          if (!fits) {
             status = RSV_ENOTCONV;
             break;
           }
-          for (int it = 0; it < 10; ++it) {
-            const double mid = 0.5 * (sub + bad);
-            cheb_expm(sh, m, mid, false);
-            if (resolved()) sub = mid;
-            else bad = mid;
-            __syncthreads();
+          if (resolved()) {
+            sub = target;
+            break;
           }
-          break;
+          if (k == jb.kmax || bk == 0.0) {
+            // the longest part of the target this basis resolves: dyadic bracket, bisection
+            bool ok = false;
+            double bad = target;
+            for (int dd = 1; dd <= jb.max_depth && !ok; ++dd) {
+              sub = ldexp(target, -dd);
+              cheb_expm(sh, m, sub, false);
+              ok = resolved();
+              __syncthreads();
+              if (!ok) bad = sub;
+            }
+            if (!ok) {
+              status = RSV_ENOTCONV;
+              break;
+            }
+            for (int it = 0; it < 10; ++it) {
+              const double mid = 0.5 * (sub + bad);
+              cheb_expm(sh, m, mid, false);
+              if (resolved()) sub = mid;
+              else bad = mid;
+              __syncthreads();
+            }
+            break;
+          }
         }
         if (tid == 0) {
           sh.beta[k - 1] = bk;
@@ -352,6 +369,7 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
       }
       if (status != RSV_OK) break;
       kmax_used = max(kmax_used, (int64_t)m);
+      m_prev = m;
       cheb_expm(sh, m, sub, true);
       // psi <- |psi| sum_l y_l s_l u_l over this thread's own amplitudes
 #pragma unroll
