@@ -10,7 +10,9 @@ first (steps 0..W-1 from |0...0>), then K steps are timed (steps W..W+K-1).  Rep
   value      simulated microseconds per wall second of the complex128 path (whole job, state
              resident in HBM),
   roofline   H psi (the dominant operation) at the step-300 parameters: algorithmic bytes
-             (40 B/amplitude c128) / average duration from HIP events on the launch stream,
+             (40 B/amplitude c128: state in, diagonal, state out) / average duration from HIP
+             events on the launch stream; the kernels form the diagonal on chip, so their
+             compulsory traffic is 32 B/amplitude (reported beside it),
   c64        the same for complex64 storage with FP64 Lanczos scalars, plus its infidelity
              against the complex128 result of the same steps,
   cpu_baseline  the CPU oracle's H psi at the same size, scaled to sim-us/s.
@@ -313,6 +315,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs128, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(gbs128 / PEAK_HBM_GBS, 4),
                      "kernel": "H|psi> at N=27 complex128 (high passes + low pass)",
+                     "bytes_per_amplitude": 40,
+                     # the state in and out only: E_b is formed on chip from small tables
+                     "compulsory_bytes_per_amplitude": 32,
+                     "achieved_compulsory": round(gbs128 * 32 / 40, 1),
                      "traffic": pmc_traffic("c128")},
         "occupations_sum": round(float(occ.sum()), 6), "n_shots": len(shots),
         "device_copy_gbps": round(cp_gbs, 1),

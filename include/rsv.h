@@ -11,8 +11,9 @@
  * (Sec. III): step k uses the mean of the 1 ns samples at floor(m) and ceil(m),
  * m = (k + 1/2) dt.  exp(-i H_k dt) psi is the Lanczos Krylov exponential of Sec. III.A,
  * grown until its a-posteriori error estimate is below the tolerance.  H psi is
- * matrix-free: the diagonal (interaction energies built once per register, detuning added
- * from the bit pattern) plus one level swap per atom scaled by the drive (Sec. III.A).
+ * matrix-free: the diagonal (interaction energies from tables built once per register,
+ * detuning added from the bit pattern) plus one level swap per atom scaled by the drive
+ * (Sec. III.A).
  *
  * Conventions
  *  - |1> is the Rydberg level, n = |1><1|; the default initial state is |0...0> (Sec. II.B).
@@ -112,24 +113,27 @@ void rsv_ctx_destroy(rsv_ctx* ctx);
 size_t rsv_ctx_bytes_in_use(const rsv_ctx* ctx);
 
 /* ------------------------------------------------------------------ register
- * Builds U_ij = C/|r_i - r_j|^6 on the host (eq. 3) and the interaction diagonal
- * E_b = sum_{i>j} U_ij n_i n_j on the device (2^N values, FP64 for RSV_C128, FP32 for
- * RSV_C64), once per register (Sec. III.A keeps only the diagonal of H).
- * n_atoms in 1..30; xyz_um is [n_atoms][3]; coincident atoms give RSV_EINVAL. */
+ * Builds U_ij = C/|r_i - r_j|^6 on the host (eq. 3) and, on the device, the tables from
+ * which the H psi kernels form the interaction diagonal E_b = sum_{i>j} U_ij n_i n_j
+ * (Sec. III.A keeps only the diagonal of H): the pair sums of the low bits and, per tile of
+ * high bits, their pair sum and couplings -- about 2^12 + 13 * 2^(N-12) FP64 values instead
+ * of 2^N.  n_atoms in 1..30; xyz_um is [n_atoms][3]; coincident atoms give RSV_EINVAL. */
 int rsv_register_create(rsv_ctx* ctx, int n_atoms, const double* xyz_um, double c6,
                         rsv_precision prec, rsv_register** out);
 void rsv_register_destroy(rsv_register* reg);
-/* Copies E into a caller device buffer of 2^N reals of the register's precision. */
+/* Writes E (2^N reals: FP64 for RSV_C128, FP32 for RSV_C64) into a caller device buffer;
+ * returns after the stream has finished. */
 int rsv_register_diagonal(rsv_register* reg, void* d_out, void* hip_stream);
 
 /* Device bytes rsv_evolve needs for a register of n_atoms: (kmax + 3) vectors (Krylov basis
- * of kmax + 1, the Lanczos residual, the high-bit H psi partial) plus the diagonal, the state
- * and the reduction buffers -- the admission formula of the server. */
+ * of kmax + 1, the Lanczos residual, the high-bit H psi partial) plus U and the diagonal
+ * tables, the state and the reduction buffers -- the admission formula of the server. */
 size_t rsv_workspace_bytes(int n_atoms, int kmax, rsv_precision prec);
 
 /* ------------------------------------------------------------------ hot path
  * One H_k psi: d_out = H_k d_in with the parameters of step `step` for the given dt
- * (Sec. III.A).  d_in, d_out: caller device buffers of 2^N amplitudes. */
+ * (Sec. III.A).  d_in, d_out: caller device buffers of 2^N amplitudes.  The kernels are
+ * enqueued on hip_stream and the call returns without waiting for them. */
 int rsv_apply_hamiltonian(rsv_register* reg, const rsv_pulses* pulses, int64_t step, int dt_ns,
                           const void* d_in, void* d_out, void* hip_stream);
 

@@ -122,8 +122,7 @@ int rsv_register_diagonal(rsv_register* reg, void* d_out, void* stream) {
   if (!reg || !d_out) return fail(RSV_EINVAL, "NULL argument");
   HIP_TRY(hipSetDevice(reg->ctx->device));
   hipStream_t s = as_stream(stream);
-  HIP_TRY(hipMemcpyAsync(d_out, reg->d_diag, (size_t(1) << reg->n) * real_bytes(reg->prec),
-                         hipMemcpyDeviceToDevice, s));
+  HIP_TRY(diag_build(reg->prec, reg->n, reg->d_ub, d_out, s));
   HIP_TRY(hipStreamSynchronize(s));
   return RSV_OK;
 }
@@ -146,8 +145,7 @@ int rsv_apply_hamiltonian(rsv_register* reg, const rsv_pulses* pl, int64_t step,
   hipStream_t s = as_stream(stream);
   const SweepIn in{d_in, nullptr, nullptr, 1.0, 0.0, 0.0, nullptr, 0.0};
   const SweepOut so{nullptr, nullptr, nullptr};
-  HIP_TRY(hpsi_sweep(reg->prec, reg->n, c, reg->d_diag, in, d_out, reg->d_hbuf, so, kAllPasses, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hpsi_sweep(reg->prec, reg->n, c, reg->d_dtab, in, d_out, reg->d_hbuf, so, kAllPasses, s));
   return RSV_OK;
 }
 

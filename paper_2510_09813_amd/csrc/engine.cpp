@@ -155,7 +155,7 @@ size_t workspace_bytes(int n, int kmax, int prec) {
 }
 
 size_t register_bytes(int n, int prec) {
-  return 32 * 32 * 8 + round_up((size_t(1) << n) * real_bytes(prec));
+  return 32 * 32 * 8 + round_up(diag_table_doubles(prec, n) * 8);
 }
 
 int check_state_args(int n, int prec) {
@@ -282,10 +282,10 @@ int register_create(rsv_ctx* ctx, Allocator* alloc, int n, const double* xyz, do
   }
   r->bytes = register_bytes(n, prec);
   r->d_ub = (double*)p;
-  r->d_diag = (char*)p + 32 * 32 * 8;
+  r->d_dtab = (double*)((char*)p + 32 * 32 * 8);
   // the host array must outlive the asynchronous copy: synchronise before returning
   hipError_t e = hipMemcpyAsync(r->d_ub, ub, sizeof ub, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = diag_build(prec, n, r->d_ub, r->d_diag, stream);
+  if (e == hipSuccess) e = diag_tables_build(prec, n, r->d_ub, r->d_dtab, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     register_destroy(r, stream);
@@ -391,7 +391,7 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
     {
       const SweepIn in{ws.basis[0], nullptr, nullptr, 1.0, 0.0, 0.0, nullptr, 0.0};
       const SweepOut so{nullptr, nullptr, ws.pdot};
-      HIP_TRY(hpsi_sweep(prec, n, c, reg->d_diag, in, ws.z, ws.t, so, kAllPasses, L.s));
+      HIP_TRY(hpsi_sweep(prec, n, c, reg->d_dtab, in, ws.z, ws.t, so, kAllPasses, L.s));
       HIP_TRY(finalize_sum(ws.pdot, np_dot, ws.dscal + 1, L.s));
       L.st->krylov_iters += 1;
       L.st->bytes_hpsi += hbytes;
@@ -405,7 +405,7 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
                        -sk1 * sk1 * sk1};
       const SweepOut so{ws.basis[k], ws.pnorm, ws.pdot};
       // single-pass sizes compute z_k in the same pass; otherwise only the forming pass
-      HIP_TRY(hpsi_sweep(prec, n, c, reg->d_diag, in, ws.z, ws.t, so, kFirstPass, L.s));
+      HIP_TRY(hpsi_sweep(prec, n, c, reg->d_dtab, in, ws.z, ws.t, so, kFirstPass, L.s));
       HIP_TRY(finalize_sum(ws.pnorm, np_norm, ws.dscal + 2 * k, L.s));
       if (single) HIP_TRY(finalize_sum(ws.pdot, np_dot, ws.dscal + 2 * k + 1, L.s));
       double ab[2];  // <u_{k-1}, z_{k-1}>, |u_k|^2
@@ -445,7 +445,7 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
       if (!single) {
         const SweepIn in2{ws.basis[k], nullptr, nullptr, 1.0, 0.0, 0.0, nullptr, 0.0};
         const SweepOut so2{nullptr, nullptr, ws.pdot};
-        HIP_TRY(hpsi_sweep(prec, n, c, reg->d_diag, in2, ws.z, ws.t, so2, kLaterPasses, L.s));
+        HIP_TRY(hpsi_sweep(prec, n, c, reg->d_dtab, in2, ws.z, ws.t, so2, kLaterPasses, L.s));
         HIP_TRY(finalize_sum(ws.pdot, np_dot, ws.dscal + 2 * k + 1, L.s));
       }
       L.st->krylov_iters += 1;

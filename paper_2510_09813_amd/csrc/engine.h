@@ -109,7 +109,7 @@ struct rsv_register {
   int prec = 0;
   double c6 = 0;
   double* d_ub = nullptr;
-  void* d_diag = nullptr;
+  double* d_dtab = nullptr;  // interaction-diagonal tables of the H psi low pass
   void* d_hbuf = nullptr;  // high-bit partial of rsv_apply_hamiltonian
   size_t bytes = 0;
   rsv::Workspace ws;
@@ -132,7 +132,7 @@ namespace rsv {
 // RSV_EINVAL for coincident atoms or non-finite input.
 int build_interactions(int n, const double* xyz, double c6, double* ub);
 
-// Builds U and the device diagonal on `stream`; memory from `alloc`; h_scal (>= 512 doubles
+// Builds U and the device diagonal tables on `stream`; memory from `alloc`; h_scal (>= 512 doubles
 // of pinned memory) is borrowed when given, else allocated.
 int register_create(rsv_ctx* ctx, Allocator* alloc, int n, const double* xyz, double c6,
                     int prec, hipStream_t stream, double* h_scal, rsv_register** out);

@@ -6,10 +6,12 @@
 // stencil on the n-dimensional hypercube, done in passes over LDS tiles:
 //
 //  * low pass:  a tile of 2^L contiguous amplitudes (L = 12 for complex128, 13 for
-//    complex64: 64 KiB of LDS, 1024 threads) covers the L least significant bits.  The
+//    complex64: 64 KiB of LDS, 512 threads) covers the L least significant bits.  The
 //    thread-index bits are flipped through the LDS tile, the remaining bits inside each
-//    thread's registers.  This pass applies the diagonal E_b (read from HBM) plus the
-//    detuning computed from the bit pattern, and adds the high-pass result t.
+//    thread's registers.  This pass applies the diagonal: the interaction energy E_b from
+//    two small FP64 tables (a 2^L table of the low-bit pairs, read from L2, and per tile the
+//    high-bit pairs and the low-high couplings), so no 2^n diagonal is read from HBM, plus
+//    the detuning from the bit pattern; and it adds the high-pass result t.
 //  * high passes (n > L): a tile of 2^r contiguous amplitudes (a run of 64 or 128 bytes)
 //    times the combinations of up to H - r high bits flips those high bits.  The first
 //    high pass writes t, later ones accumulate into it.  A last pass with few bits left
@@ -36,11 +38,17 @@ namespace {
 // better; the planner gives each pass the longest run the bit count allows).
 template <class R> struct Geo;
 template <> struct Geo<double> {
-  static constexpr int L = 12, NL = 1024, H = 12, RL = 3, RLW = 6, NH = 1024;
+  static constexpr int L = 12, NL = 512, H = 12, RL = 3, RLW = 6, NH = 1024;
 };
 template <> struct Geo<float> {
-  static constexpr int L = 13, NL = 1024, H = 12, RL = 3, RLW = 6, NH = 1024;
+  static constexpr int L = 13, NL = 512, H = 12, RL = 3, RLW = 6, NH = 1024;
 };
+// Low-pass threads: NL (8 amplitudes per thread at L bits, room for every operand in
+// registers); the per-site complex128 form, heavier in arithmetic, runs 1024 threads.
+template <class R, int CM>
+constexpr int lo_threads() {
+  return CM == kCoefSite && sizeof(R) == 8 ? 1024 : Geo<R>::NL;
+}
 static_assert(Geo<double>::RL == 3 && Geo<double>::RLW == 6 && Geo<float>::RL == 3 &&
                   Geo<float>::RLW == 6,
               "launch_hi instantiates run lengths 3..6");
@@ -78,8 +86,9 @@ struct PassArgs {
   // high pass
   Cx<R>* tb;
   int accumulate, a, f0, f1;
-  // low pass
-  const R* diag;
+  // low pass: interaction-diagonal tables (elo: 2^L values, etile: L + 1 per tile)
+  const double* elo;
+  const double* etile;
   Cx<R>* out;
   double* part_dot;  // optional: per-workgroup Re<u, out>
   uint32_t nblk;
@@ -200,14 +209,23 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
   C v[A], tv[A];
   R dg[A];
   double nrm = 0.0;
-  // every HBM operand is requested before the barrier, so the loads of the diagonal and of
-  // the high-pass partial overlap those of the state
+  // every operand is requested before the barrier, so the loads of the high-pass partial
+  // and the diagonal table overlap those of the state
+  const double* et = p.etile + (size_t)blk * (LB + 1);
+  double eth = et[0];  // the tile's high-bit pairs plus the couplings of the thread bits
+#pragma unroll
+  for (int q = 0; q < TB; ++q)
+    if ((tid >> q) & 1u) eth += et[1 + q];
 #pragma unroll
   for (int s = 0; s < A; ++s) {
     const uint32_t e = tid + NT * s;
     v[s] = form<R>(p, b1, base + e);
-    dg[s] = p.diag[base + e];
     tv[s] = p.tb ? p.tb[base + e] : C{0, 0};
+    double es = eth;
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if ((s >> q) & 1) es += et[1 + TB + q];
+    dg[s] = (R)(p.elo[e] + es);
   }
 #pragma unroll
   for (int s = 0; s < A; ++s) tile[tid + NT * s] = v[s];
@@ -270,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void hpsi_small_kernel(const StepCoef c, co
   }
   __syncthreads();
   if (tid < dim) {
-    const R d = p.diag[tid] + detuning<R, CM>(c, lut, tid);
+    const R d = (R)(p.elo[tid] + p.etile[0]) + detuning<R, CM>(c, lut, tid);
     C acc = {d * v.x, d * v.y};
     DriveSum<R, CM> ds;
     for (int q = 0; q < c.n; ++q) ds.add(c, q, (tid >> q) & 1, tile[tid ^ (1u << q)]);
@@ -306,16 +324,19 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
   const uint32_t obase = ((blk & ((1u << gap) - 1u)) << RL) | ((blk >> gap) << (p.a + G));
 
   const double b1 = input_coef1(p);
-  C v[A];
+  C v[A], tv[A];
   uint32_t gi[A];
   double nrm = 0.0;
+  // the partial being accumulated is requested with the state, before the barrier
 #pragma unroll
   for (int s = 0; s < A; ++s) {
     const uint32_t e = tid + NT * s;
     gi[s] = obase | (e & ((1u << RL) - 1u)) | ((e >> RL) << p.a);
     v[s] = form<R>(p, b1, gi[s]);
-    tile[e] = v[s];
+    tv[s] = p.accumulate ? p.tb[gi[s]] : C{0, 0};
   }
+#pragma unroll
+  for (int s = 0; s < A; ++s) tile[tid + NT * s] = v[s];
   if (p.u_out) {
 #pragma unroll
     for (int s = 0; s < A; ++s) {
@@ -338,7 +359,7 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
       ds.add(c, q, (e >> eb) & 1u, nb);
     }
     ds.finish(c, acc);
-    if (p.accumulate) cadd<R>(acc, p.tb[gi[s]]);
+    if (p.accumulate) cadd<R>(acc, tv[s]);
     p.tb[gi[s]] = acc;
   }
   if (p.part_norm) {
@@ -349,7 +370,7 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
 
 template <class R, int LB, int CM>
 void launch_lo(const StepCoef& c, PassArgs<R> p, int n, hipStream_t s) {
-  constexpr int NT = Geo<R>::NL < (1 << LB) ? Geo<R>::NL : (1 << LB);
+  constexpr int NT = lo_threads<R, CM>() < (1 << LB) ? lo_threads<R, CM>() : (1 << LB);
   p.nblk = 1u << (n - LB);
   hipLaunchKernelGGL((hpsi_lo_kernel<R, LB, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p);
 }
@@ -380,7 +401,7 @@ void launch_hi(int rl, const StepCoef& c, const PassArgs<R>& p, hipStream_t s) {
 }
 
 template <class R, int CM>
-hipError_t sweep_t(int n, const StepCoef& c, const void* diag, const SweepIn& in, void* out,
+hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& in, void* out,
                    void* tbuf, const SweepOut& so, int part, hipStream_t s) {
   PassArgs<R> base{};
   base.x0 = (const Cx<R>*)in.x0;
@@ -391,7 +412,9 @@ hipError_t sweep_t(int n, const StepCoef& c, const void* diag, const SweepIn& in
   base.a2 = in.a2;
   base.dot = in.dot;
   base.dot_coef = in.dot_coef;
-  base.diag = (const R*)diag;
+  const int lbits = make_tile_plan(sizeof(R) == 8 ? kC128 : kC64, n).lo_bits;
+  base.elo = dtab;
+  base.etile = dtab + (size_t(1) << lbits);
   base.out = (Cx<R>*)out;
 
   const bool first = part != kLaterPasses, later = part != kFirstPass;
@@ -447,12 +470,12 @@ hipError_t sweep_t(int n, const StepCoef& c, const void* diag, const SweepIn& in
 }
 
 template <class R>
-hipError_t sweep_r(int n, const StepCoef& c, const void* diag, const SweepIn& in, void* out,
+hipError_t sweep_r(int n, const StepCoef& c, const double* dtab, const SweepIn& in, void* out,
                    void* tbuf, const SweepOut& so, int part, hipStream_t s) {
   switch (c.mode) {
-    case kCoefReal: return sweep_t<R, kCoefReal>(n, c, diag, in, out, tbuf, so, part, s);
-    case kCoefSite: return sweep_t<R, kCoefSite>(n, c, diag, in, out, tbuf, so, part, s);
-    default: return sweep_t<R, kCoefUniform>(n, c, diag, in, out, tbuf, so, part, s);
+    case kCoefReal: return sweep_t<R, kCoefReal>(n, c, dtab, in, out, tbuf, so, part, s);
+    case kCoefSite: return sweep_t<R, kCoefSite>(n, c, dtab, in, out, tbuf, so, part, s);
+    default: return sweep_t<R, kCoefUniform>(n, c, dtab, in, out, tbuf, so, part, s);
   }
 }
 
@@ -517,10 +540,10 @@ int sweep_passes(int prec, int n) {
   return 1 + make_tile_plan(prec, n).n_hi_passes;
 }
 
-hipError_t hpsi_sweep(int prec, int n, const StepCoef& c, const void* diag, const SweepIn& in,
+hipError_t hpsi_sweep(int prec, int n, const StepCoef& c, const double* dtab, const SweepIn& in,
                       void* out, void* tbuf, const SweepOut& so, int part, hipStream_t s) {
-  if (prec == kC128) return sweep_r<double>(n, c, diag, in, out, tbuf, so, part, s);
-  return sweep_r<float>(n, c, diag, in, out, tbuf, so, part, s);
+  if (prec == kC128) return sweep_r<double>(n, c, dtab, in, out, tbuf, so, part, s);
+  return sweep_r<float>(n, c, dtab, in, out, tbuf, so, part, s);
 }
 
 }  // namespace rsv

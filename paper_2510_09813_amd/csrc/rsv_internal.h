@@ -74,8 +74,9 @@ struct SweepOut {
 enum SweepPart : int { kAllPasses = 0, kFirstPass = 1, kLaterPasses = 2 };
 
 // out = H u over all passes of the tile plan (or only the first / only the later ones);
-// tbuf (one vector) holds the high-bit partial when n > lo_bits.
-hipError_t hpsi_sweep(int prec, int n, const StepCoef& c, const void* diag, const SweepIn& in,
+// dtab holds the interaction-diagonal tables (diag_tables_build); tbuf (one vector) holds
+// the high-bit partial when n > lo_bits.
+hipError_t hpsi_sweep(int prec, int n, const StepCoef& c, const double* dtab, const SweepIn& in,
                       void* out, void* tbuf, const SweepOut& so, int part, hipStream_t s);
 int64_t sweep_num_partials(int prec, int n);   // the largest partial count of any pass
 int64_t sweep_norm_partials(int prec, int n);  // partials of |u|^2 (first pass)
@@ -85,6 +86,14 @@ int sweep_passes(int prec, int n);
 // --------------------------------------------------------------------------- diagonal
 // E_b = sum_{p<q} Ub[p][q] b_p b_q for all b < 2^n; Ub is 32x32 FP64, bit-indexed, on device.
 hipError_t diag_build(int prec, int n, const double* d_ub, void* diag, hipStream_t s);
+// The low pass forms E_b from two FP64 tables instead of reading a stored diagonal
+// (L = the plan's lo_bits, b = (t << L) | e):
+//   elo[e]                   = sum over pairs of set bits inside [0, L)        (2^L values)
+//   etile[t (L + 1)]         = sum over pairs of set bits of t << L, above L
+//   etile[t (L + 1) + 1 + p] = sum over set bits q >= L of t << L of Ub[p][q]  (p < L)
+// so E_b = elo[e] + etile[t (L+1)] + sum_{p < L, e_p = 1} etile[t (L+1) + 1 + p].
+size_t diag_table_doubles(int prec, int n);
+hipError_t diag_tables_build(int prec, int n, const double* d_ub, double* dtab, hipStream_t s);
 
 // --------------------------------------------------------------------------- vectors
 int64_t vec_num_partials(int prec, int n);

@@ -55,18 +55,34 @@ __global__ __launch_bounds__(kBlock) void norm2_kernel(const Cx<R>* __restrict__
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// One workgroup of 256 threads: thread t sums a contiguous slice in order, then a fixed tree.
-__global__ __launch_bounds__(kBlock) void finalize_kernel(const double* __restrict__ partial,
-                                                          const int64_t count,
-                                                          double* __restrict__ dst) {
-  __shared__ double red[4];
-  const int64_t per = (count + kBlock - 1) / kBlock;
-  const int64_t lo = (int64_t)threadIdx.x * per;
-  const int64_t hi = lo + per < count ? lo + per : count;
-  double acc = 0.0;
-  for (int64_t i = lo; i < hi; ++i) acc += partial[i];
-  const double t = block_sum_256(acc, red);
-  if (threadIdx.x == 0) dst[0] = t;
+// One workgroup of 1024 threads: thread t sums partial[t], partial[t + 1024], ... in order
+// (coalesced loads, four independent chains), then a fixed tree over the workgroup.
+constexpr int kFinalizeThreads = 1024;
+__global__ __launch_bounds__(kFinalizeThreads) void finalize_kernel(const double* __restrict__ partial,
+                                                                    const int64_t count,
+                                                                    double* __restrict__ dst) {
+  __shared__ double red[kFinalizeThreads / 64];
+  constexpr int64_t S = kFinalizeThreads;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * S < count; i += 4 * S) {
+    a0 += partial[i];
+    a1 += partial[i + S];
+    a2 += partial[i + 2 * S];
+    a3 += partial[i + 3 * S];
+  }
+  for (; i < count; i += S) a0 += partial[i];
+  double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kFinalizeThreads / 64; ++w) t += red[w];
+    dst[0] = t;
+  }
 }
 
 template <class RS, class RD>
@@ -116,7 +132,7 @@ hipError_t norm2_partial(int prec, int n, const void* x, double* partial, hipStr
 }
 
 hipError_t finalize_sum(const double* partial, int64_t count, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, s, partial, count, dst);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, partial, count, dst);
   return hipGetLastError();
 }
 
