@@ -44,10 +44,10 @@ template <> struct Geo<float> {
   static constexpr int L = 13, NL = 512, H = 12, RL = 3, RLW = 6, NH = 1024;
 };
 // Low-pass threads: NL (8 amplitudes per thread at L bits, room for every operand in
-// registers); the per-site complex128 form, heavier in arithmetic, runs 1024 threads.
+// registers).
 template <class R, int CM>
 constexpr int lo_threads() {
-  return CM == kCoefSite && sizeof(R) == 8 ? 1024 : Geo<R>::NL;
+  return Geo<R>::NL;
 }
 static_assert(Geo<double>::RL == 3 && Geo<double>::RLW == 6 && Geo<float>::RL == 3 &&
                   Geo<float>::RLW == 6,
@@ -239,21 +239,52 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
   __syncthreads();
 
   double dot = 0.0;
+  if constexpr (CM == kCoefSite) {
+    // per-site couplings: a thread-index bit has the same level in all of this thread's
+    // amplitudes, so its coefficient is chosen once and applied to all of them
+    C acc[A];
 #pragma unroll
-  for (int s = 0; s < A; ++s) {
-    const uint32_t e = tid + NT * s;
-    const uint32_t b = base + e;
-    const R d = dg[s] + detuning<R, CM>(c, lut, b);
-    C acc = {d * v[s].x, d * v[s].y};
-    DriveSum<R, CM> ds;
+    for (int s = 0; s < A; ++s) {
+      const R d = dg[s] + detuning<R, CM>(c, lut, base + tid + NT * s);
+      acc[s] = C{d * v[s].x, d * v[s].y};
+    }
 #pragma unroll
-    for (int q = 0; q < TB; ++q) ds.add(c, q, (tid >> q) & 1, tile[e ^ (1u << q)]);
+    for (int q = 0; q < TB; ++q) {
+      const bool bit = (tid >> q) & 1u;
+      const R cr = (R)(bit ? c.up_re[q] : c.dn_re[q]);
+      const R ci = (R)(bit ? c.up_im[q] : c.dn_im[q]);
 #pragma unroll
-    for (int q = 0; q < RB; ++q) ds.add(c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
-    ds.finish(c, acc);
-    if (p.tb) cadd<R>(acc, tv[s]);
-    p.out[b] = acc;
-    dot += (double)v[s].x * (double)acc.x + (double)v[s].y * (double)acc.y;
+      for (int s = 0; s < A; ++s) {
+        const C nb = tile[(tid + NT * s) ^ (1u << q)];
+        acc[s].x += cr * nb.x - ci * nb.y;
+        acc[s].y += cr * nb.y + ci * nb.x;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < A; ++s) {
+#pragma unroll
+      for (int q = 0; q < RB; ++q) cmad<R>(acc[s], c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
+      if (p.tb) cadd<R>(acc[s], tv[s]);
+      p.out[base + tid + NT * s] = acc[s];
+      dot += (double)v[s].x * (double)acc[s].x + (double)v[s].y * (double)acc[s].y;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < A; ++s) {
+      const uint32_t e = tid + NT * s;
+      const uint32_t b = base + e;
+      const R d = dg[s] + detuning<R, CM>(c, lut, b);
+      C acc = {d * v[s].x, d * v[s].y};
+      DriveSum<R, CM> ds;
+#pragma unroll
+      for (int q = 0; q < TB; ++q) ds.add(c, q, (tid >> q) & 1, tile[e ^ (1u << q)]);
+#pragma unroll
+      for (int q = 0; q < RB; ++q) ds.add(c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
+      ds.finish(c, acc);
+      if (p.tb) cadd<R>(acc, tv[s]);
+      p.out[b] = acc;
+      dot += (double)v[s].x * (double)acc.x + (double)v[s].y * (double)acc.y;
+    }
   }
   if (p.part_norm) {
     const double t = wg_sum<NT>(nrm, red);
