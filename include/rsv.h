@@ -83,7 +83,12 @@ typedef struct {
  * kmax:       maximum Krylov dimension, 2..64.  Without convergence the step is split into
  *             sub-steps with the same H_k (exact), at most max_substep_depth halvings deep.
  * first_step, n_steps: evolve steps [first_step, first_step + n_steps); n_steps < 0 means up
- *             to the end of the pulse.  Stepping is Markov, so (k, psi_k) is a checkpoint. */
+ *             to the end of the pulse.  Stepping is Markov, so (k, psi_k) is a checkpoint.
+ * reorth:     0 = the three-term Lanczos recurrence (default); 1 = every new Krylov vector is
+ *             also orthogonalised against all stored ones (classical Gram-Schmidt, FP64
+ *             inner products), at the cost of reading the basis once more per iteration.
+ *             The paper leaves orthogonalisation open; the loss of orthogonality found is
+ *             reported in rsv_stats.ortho_loss. */
 typedef struct {
   int dt_ns;
   double tol;
@@ -91,6 +96,7 @@ typedef struct {
   int max_substep_depth;
   int64_t first_step;
   int64_t n_steps;
+  int reorth;
 } rsv_evolve_opts;
 
 typedef struct {
@@ -101,6 +107,7 @@ typedef struct {
   double norm_final;      /* |psi| after the last step (1 up to rounding) */
   double seconds;         /* wall time of the evolution, entry to final synchronisation */
   double bytes_hpsi;      /* algorithmic HBM bytes of the H psi passes */
+  double ortho_loss;      /* reorth = 1: largest |<v_l, u>| / |u| removed from a new vector */
 } rsv_stats;
 
 /* ------------------------------------------------------------------ context */

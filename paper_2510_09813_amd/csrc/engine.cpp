@@ -146,7 +146,10 @@ size_t vec_bytes(int n, int prec) { return (size_t(1) << n) * amp_bytes(prec); }
 size_t partial_doubles(int n, int prec) {
   int64_t a = sweep_num_partials(prec, n), b = vec_num_partials(prec, n);
   int64_t c = occ_num_partials(n), d = sample_scratch_doubles(n);
-  return (size_t)std::max(std::max(a, b), std::max(c, d));
+  // the two partial arrays are adjacent: together they hold a group of re-orthogonalisation
+  // inner products (2 kDotGroup rows of vec_num_partials)
+  const int64_t e = (int64_t)kDotGroup * b;
+  return (size_t)std::max(std::max(std::max(a, b), std::max(c, d)), e);
 }
 
 size_t workspace_bytes(int n, int kmax, int prec) {
@@ -221,6 +224,7 @@ int check_opts(const rsv_evolve_opts* o, const rsv_pulses* pl, int64_t* first, i
   if (o->kmax < 2 || o->kmax > kMaxKrylov) return fail(RSV_EINVAL, "kmax must be in 2..64");
   if (o->max_substep_depth < 0 || o->max_substep_depth > 40)
     return fail(RSV_EINVAL, "max_substep_depth must be in 0..40");
+  if (o->reorth != 0 && o->reorth != 1) return fail(RSV_EINVAL, "reorth must be 0 or 1");
   const int64_t K = (pl->n_samples - 1) / o->dt_ns;
   if (o->first_step < 0 || o->first_step > K) return fail(RSV_EINVAL, "first_step out of range");
   const int64_t cnt = o->n_steps < 0 ? K - o->first_step : o->n_steps;
@@ -338,8 +342,11 @@ int workspace_acquire(rsv_register* reg, int kmax) {
 // ------------------------------------------------------------------------------ Lanczos
 namespace {
 
-// Device scalars: slot 2k holds |u_k|^2, slot 2k+1 holds Re<u_k, H u_k>; kNormSlot |psi|^2.
+// Device scalars: slot 2k holds |u_k|^2, slot 2k+1 holds Re<u_k, H u_k>; kNormSlot |psi|^2;
+// from kDotSlot, Re and Im <u_l, u_k> of the re-orthogonalisation (2 kMaxKrylov values).
 constexpr int kNormSlot = 2 * kMaxKrylov + 4;
+constexpr int kDotSlot = 256;
+static_assert(kDotSlot + 2 * kMaxKrylov <= (int)(kScalarBytes / 8), "device scalar block");
 
 struct Lanczos {
   rsv_register* reg;
@@ -360,6 +367,47 @@ int fetch_scalars(Lanczos& L, int first_slot, int count, double* out) {
   return RSV_OK;
 }
 
+// Full re-orthogonalisation of the new vector u_k (classical Gram-Schmidt with FP64 inner
+// products): u_k <- u_k - sum_{l<k} v_l <v_l, u_k>, v_l = s_l u_l.  The result goes to a
+// fresh buffer that becomes basis[k] (the old one becomes the high-pass partial t, which
+// the caller recomputes).  b2 is |u_k|^2 before on entry and after on return.
+int reorthogonalise(Lanczos& L, int k, double* b2) {
+  rsv_register* reg = L.reg;
+  Workspace& ws = reg->ws;
+  const int n = reg->n, prec = reg->prec;
+  const int64_t nw = vec_num_partials(prec, n);
+  for (int l0 = 0; l0 < k; l0 += kDotGroup) {
+    DotGroup d{};
+    d.g = std::min(kDotGroup, k - l0);
+    for (int g = 0; g < d.g; ++g) d.x[g] = ws.basis[l0 + g];
+    HIP_TRY(multi_dot(prec, n, d, ws.basis[k], ws.pnorm, L.s));
+    HIP_TRY(finalize_rows(ws.pnorm, nw, 2 * d.g, ws.dscal + kDotSlot + 2 * l0, L.s));
+  }
+  double dots[2 * kMaxKrylov];
+  RSV_TRY(fetch_scalars(L, kDotSlot, 2 * k, dots));
+  CombineCoef cc;
+  std::memset(&cc, 0, sizeof cc);
+  cc.m = k + 1;
+  cc.re[0] = 1.0;
+  cc.x[0] = ws.basis[k];
+  double loss = 0.0;
+  for (int l = 0; l < k; ++l) {
+    const double sl = L.scale[l];
+    if (!std::isfinite(dots[2 * l]) || !std::isfinite(dots[2 * l + 1]))
+      return fail(RSV_ENUMERIC, "re-orthogonalisation inner product not finite");
+    cc.re[l + 1] = -sl * sl * dots[2 * l];
+    cc.im[l + 1] = -sl * sl * dots[2 * l + 1];
+    cc.x[l + 1] = ws.basis[l];
+    loss = std::max(loss, sl * std::hypot(dots[2 * l], dots[2 * l + 1]));
+  }
+  if (*b2 > 0.0) L.st->ortho_loss = std::max(L.st->ortho_loss, loss / std::sqrt(*b2));
+  HIP_TRY(krylov_combine(prec, n, cc, ws.t, ws.pnorm, L.s));
+  HIP_TRY(finalize_sum(ws.pnorm, nw, ws.dscal + 2 * k, L.s));
+  std::swap(ws.basis[k], ws.t);
+  RSV_TRY(fetch_scalars(L, 2 * k, 1, b2));
+  return RSV_OK;
+}
+
 // |[exp(-i h T_m) e_1]_{m-1}| for the current T_m.
 int last_component(Lanczos& L, int m, double h, double* out) {
   if (tridiag_expm_last(m, L.alpha, L.beta, h, out, L.work.data()) != 0)
@@ -375,7 +423,8 @@ int last_component(Lanczos& L, int m, double h, double* out) {
 // (= H v_{k-1} - alpha_{k-1} v_{k-1} - beta_{k-2} v_{k-2}) in its first pass, stores it,
 // and returns |u_k|^2 = beta_{k-1}^2; the host then tests convergence of the m = k
 // dimensional Krylov approximation before the later passes compute z_k = H u_k.
-int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, int max_depth) {
+int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, int max_depth,
+              bool reorth) {
   rsv_register* reg = L.reg;
   Workspace& ws = reg->ws;
   const int n = reg->n, prec = reg->prec;
@@ -413,6 +462,11 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
       if (!std::isfinite(ab[0]) || !std::isfinite(ab[1]))
         return fail(RSV_ENUMERIC, "Lanczos coefficient not finite at iteration %d", k);
       L.alpha[k - 1] = sk1 * sk1 * ab[0];
+      if (reorth) {
+        RSV_TRY(reorthogonalise(L, k, &ab[1]));
+        if (!std::isfinite(ab[1]))
+          return fail(RSV_ENUMERIC, "Lanczos coefficient not finite at iteration %d", k);
+      }
       const double bk = std::sqrt(std::max(ab[1], 0.0));  // beta_{k-1}
       m = k;
       double ylast = 0.0;
@@ -442,10 +496,13 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
       }
       L.beta[k - 1] = bk;
       L.scale[k] = 1.0 / bk;
-      if (!single) {
+      if (!single || reorth) {
+        // z_k = H u_k: the remaining passes, or all of them when u_k was re-orthogonalised
+        // after the forming pass
         const SweepIn in2{ws.basis[k], nullptr, nullptr, 1.0, 0.0, 0.0, nullptr, 0.0};
         const SweepOut so2{nullptr, nullptr, ws.pdot};
-        HIP_TRY(hpsi_sweep(prec, n, c, reg->d_dtab, in2, ws.z, ws.t, so2, kLaterPasses, L.s));
+        HIP_TRY(hpsi_sweep(prec, n, c, reg->d_dtab, in2, ws.z, ws.t, so2,
+                           reorth ? kAllPasses : kLaterPasses, L.s));
         HIP_TRY(finalize_sum(ws.pdot, np_dot, ws.dscal + 2 * k + 1, L.s));
       }
       L.st->krylov_iters += 1;
@@ -501,7 +558,7 @@ int evolve(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_opts* o, vo
   const double tau = o->dt_ns * 1e-3;  // us
   for (int64_t k = first; k < first + count; ++k) {
     const StepCoef c = step_coef(pl, n, k, o->dt_ns);
-    RSV_TRY(propagate(L, c, tau, o->tol, o->kmax, o->max_substep_depth));
+    RSV_TRY(propagate(L, c, tau, o->tol, o->kmax, o->max_substep_depth, o->reorth != 0));
     st->steps += 1;
   }
   HIP_TRY(hipMemcpyAsync(d_psi, ws.basis[0], vb, hipMemcpyDeviceToDevice, s));

@@ -35,11 +35,20 @@ struct StepCoef {
   double delta[kMaxAtoms];
 };
 
-// Krylov combination: out = sum_l (re_l + i im_l) * x_l, x_l device vectors.
+// Krylov combination: out = sum_l (re_l + i im_l) * x_l, x_l device vectors (up to the whole
+// basis plus one more vector, for re-orthogonalisation).
+constexpr int kMaxCombine = kMaxKrylov + 1;
 struct CombineCoef {
   int m;
-  double re[kMaxKrylov], im[kMaxKrylov];
-  const void* x[kMaxKrylov];
+  double re[kMaxCombine], im[kMaxCombine];
+  const void* x[kMaxCombine];
+};
+
+// Inner products <x_g, y> = sum_b conj(x_g[b]) y[b] of up to kDotGroup vectors with one y.
+constexpr int kDotGroup = 8;
+struct DotGroup {
+  int g;
+  const void* x[kDotGroup];
 };
 
 // --------------------------------------------------------------------------- H|psi>
@@ -104,6 +113,12 @@ hipError_t krylov_combine(int prec, int n, const CombineCoef& c, void* out, doub
 hipError_t norm2_partial(int prec, int n, const void* x, double* partial, hipStream_t s);
 // dst[0] = sum of partial[0..count) in a fixed order (one workgroup).
 hipError_t finalize_sum(const double* partial, int64_t count, double* dst, hipStream_t s);
+// dst[r] = sum of partial[r * count .. (r + 1) * count) for r < rows, the same fixed order.
+hipError_t finalize_rows(const double* partial, int64_t count, int rows, double* dst,
+                         hipStream_t s);
+// Partials of Re and Im <x_g, y>: partial[(2 g + c) * vec_num_partials + w], c = 0 re, 1 im.
+hipError_t multi_dot(int prec, int n, const DotGroup& d, const void* y, double* partial,
+                     hipStream_t s);
 // Precision conversion for state import/export: complex128 <-> storage precision.
 hipError_t convert_from_c128(int prec, int n, const void* src_c128, void* dst, hipStream_t s);
 hipError_t convert_to_c128(int prec, int n, const void* src, void* dst_c128, hipStream_t s);

@@ -591,7 +591,8 @@ int rsv_server_submit(rsv_server* srv, const rsv_job_desc* jd, uint64_t* job_id)
   }
   j->first_step = first;
   j->n_steps = count;
-  j->packed = n <= std::min(srv->opts.pack_max_atoms, packed_max_atoms(jd->prec));
+  // the packed kernel runs the three-term recurrence only
+  j->packed = !jd->opts.reorth && n <= std::min(srv->opts.pack_max_atoms, packed_max_atoms(jd->prec));
   if (j->packed) {
     packed_sizes(*j);
     // too large for one staging buffer: the plain path takes it

@@ -18,7 +18,7 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombineCoef c,
                                                          double* __restrict__ partial,
                                                          const size_t count) {
   __shared__ double red[4];
-  __shared__ const Cx<R>* ptr[kMaxKrylov];
+  __shared__ const Cx<R>* ptr[kMaxCombine];
   if (threadIdx.x < c.m) ptr[threadIdx.x] = (const Cx<R>*)c.x[threadIdx.x];
   __syncthreads();
   double acc = 0.0;
@@ -55,13 +55,46 @@ __global__ __launch_bounds__(kBlock) void norm2_kernel(const Cx<R>* __restrict__
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// One workgroup of 1024 threads: thread t sums partial[t], partial[t + 1024], ... in order
-// (coalesced loads, four independent chains), then a fixed tree over the workgroup.
+// Conjugate inner products of up to kDotGroup vectors with y, FP64 accumulation.
+template <class R>
+__global__ __launch_bounds__(kBlock) void multi_dot_kernel(const DotGroup d,
+                                                           const Cx<R>* __restrict__ y,
+                                                           double* __restrict__ partial,
+                                                           const size_t count) {
+  __shared__ double red[4];
+  double acc[2 * kDotGroup];
+#pragma unroll
+  for (int j = 0; j < 2 * kDotGroup; ++j) acc[j] = 0.0;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+    const Cx<R> yi = y[i];
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) {
+      if (g < d.g) {
+        const Cx<R> xi = ((const Cx<R>*)d.x[g])[i];
+        acc[2 * g] += (double)xi.x * (double)yi.x + (double)xi.y * (double)yi.y;
+        acc[2 * g + 1] += (double)xi.x * (double)yi.y - (double)xi.y * (double)yi.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2 * kDotGroup; ++j) {
+    if (j < 2 * d.g) {
+      const double t = block_sum_256(acc[j], red);
+      if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
+// One workgroup of 1024 threads per row: thread t sums partial[t], partial[t + 1024], ... in
+// order (coalesced loads, four independent chains), then a fixed tree over the workgroup.
 constexpr int kFinalizeThreads = 1024;
-__global__ __launch_bounds__(kFinalizeThreads) void finalize_kernel(const double* __restrict__ partial,
+__global__ __launch_bounds__(kFinalizeThreads) void finalize_kernel(const double* __restrict__ all,
                                                                     const int64_t count,
-                                                                    double* __restrict__ dst) {
+                                                                    double* __restrict__ dst_all) {
   __shared__ double red[kFinalizeThreads / 64];
+  const double* partial = all + (size_t)blockIdx.x * count;
+  double* dst = dst_all + blockIdx.x;
   constexpr int64_t S = kFinalizeThreads;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int64_t i = threadIdx.x;
@@ -132,7 +165,27 @@ hipError_t norm2_partial(int prec, int n, const void* x, double* partial, hipStr
 }
 
 hipError_t finalize_sum(const double* partial, int64_t count, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, partial, count, dst);
+  return finalize_rows(partial, count, 1, dst, s);
+}
+
+hipError_t finalize_rows(const double* partial, int64_t count, int rows, double* dst,
+                         hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(rows), dim3(kFinalizeThreads), 0, s, partial, count,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t multi_dot(int prec, int n, const DotGroup& d, const void* y, double* partial,
+                     hipStream_t s) {
+  const size_t count = size_t(1) << n;
+  const uint32_t g = stream_grid(count, kPerThread);
+  if (prec == kC128)
+    hipLaunchKernelGGL(multi_dot_kernel<double>, dim3(g), dim3(kBlock), 0, s, d,
+                       (const double2*)y, partial, count);
+  else
+    hipLaunchKernelGGL(multi_dot_kernel<float>, dim3(g), dim3(kBlock), 0, s, d,
+                       (const float2*)y, partial, count);
   return hipGetLastError();
 }
 

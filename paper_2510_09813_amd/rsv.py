@@ -46,13 +46,13 @@ class Pulses(C.Structure):
 class EvolveOpts(C.Structure):
     _fields_ = [("dt_ns", C.c_int), ("tol", C.c_double), ("kmax", C.c_int),
                 ("max_substep_depth", C.c_int), ("first_step", C.c_int64),
-                ("n_steps", C.c_int64)]
+                ("n_steps", C.c_int64), ("reorth", C.c_int)]
 
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("krylov_iters", C.c_int64), ("krylov_max", C.c_int64),
                 ("substeps", C.c_int64), ("norm_final", C.c_double), ("seconds", C.c_double),
-                ("bytes_hpsi", C.c_double)]
+                ("bytes_hpsi", C.c_double), ("ortho_loss", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -151,8 +151,8 @@ class PulseArrays:
 
 
 def evolve_opts(dt_ns: int, tol: float = 1e-10, kmax: int = 30, max_substep_depth: int = 12,
-                first_step: int = 0, n_steps: int = -1) -> EvolveOpts:
-    return EvolveOpts(dt_ns, tol, kmax, max_substep_depth, first_step, n_steps)
+                first_step: int = 0, n_steps: int = -1, reorth: int = 0) -> EvolveOpts:
+    return EvolveOpts(dt_ns, tol, kmax, max_substep_depth, first_step, n_steps, reorth)
 
 
 # ------------------------------------------------------------------------- C calls

@@ -26,10 +26,11 @@ def ctx():
     rsv.rsv_ctx_destroy(c)
 
 
-def gpu_run(ctx, w, prec, psi0=None, first=0, steps=-1, tol=None, kmax=None, depth=12, c6=None):
+def gpu_run(ctx, w, prec, psi0=None, first=0, steps=-1, tol=None, kmax=None, depth=12, c6=None,
+            reorth=0):
     reg = rsv.rsv_register_create(ctx, w.xyz, w.c6 if c6 is None else c6, prec)
     tol = tol if tol is not None else (w.tol if prec == "c128" else max(w.tol, 1e-7))
-    opts = rsv.evolve_opts(w.dt_ns, tol, kmax or w.kmax, depth, first, steps)
+    opts = rsv.evolve_opts(w.dt_ns, tol, kmax or w.kmax, depth, first, steps, reorth)
     try:
         res = rsv.rsv_evolve(reg, rsv.PulseArrays(w.omega, w.delta, w.phi), opts, psi0)
         try:
@@ -143,6 +144,32 @@ def test_n27_c64_against_c128(ctx):
     assert np.abs(occ_a - occ_b).max() <= 1e-5
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_full_reorthogonalisation(ctx, prec):
+    """reorth = 1 (every new vector orthogonalised against the whole basis): chain10 matches
+    the dense oracle, and a 16-atom window matches the Krylov oracle (which re-orthogonalises
+    too) and the three-term run; the orthogonality lost by the recurrence is reported."""
+    w = wl.chain10()
+    ref = evolve.evolve_workload(w, method="dense")
+    psi, occ, st, res = gpu_run(ctx, w, prec, reorth=1)
+    rsv.rsv_result_destroy(res)
+    check(psi, occ, ref, prec)
+    assert st["steps"] == 100 and st["ortho_loss"] > 0.0
+    w = wl.random27(n_atoms=16)
+    h, _, _, r = gpu_run(ctx, w, prec, steps=100)  # the state at step 100
+    rsv.rsv_result_destroy(r)
+    ref = evolve.evolve_workload(w, steps=4, first_step=100, psi0=h)
+    a, _, st_a, r = gpu_run(ctx, w, prec, psi0=h, first=100, steps=4, reorth=1)
+    rsv.rsv_result_destroy(r)
+    b, _, st_b, r = gpu_run(ctx, w, prec, psi0=h, first=100, steps=4)
+    rsv.rsv_result_destroy(r)
+    bound = INFID[prec]
+    assert observables.fidelity_loss(ref, a) <= bound
+    assert observables.fidelity_loss(b, a) <= bound
+    assert st_a["ortho_loss"] > 0.0 and st_b["ortho_loss"] == 0.0
+    assert abs(st_a["krylov_iters"] - st_b["krylov_iters"]) <= 4
+
+
 def test_determinism_and_checkpoint(ctx):
     """Fixed-order reductions: two runs are bitwise equal, and a run split at a step boundary
     (state handed back in) equals the whole run bitwise (stepping is Markov)."""
@@ -219,7 +246,7 @@ def test_invalid_options(ctx):
     pl = rsv.PulseArrays(w.omega, w.delta)
     for opts in [rsv.evolve_opts(7), rsv.evolve_opts(10, tol=0.0), rsv.evolve_opts(10, kmax=1),
                  rsv.evolve_opts(10, kmax=65), rsv.evolve_opts(10, first_step=101),
-                 rsv.evolve_opts(10, first_step=50, n_steps=60)]:
+                 rsv.evolve_opts(10, first_step=50, n_steps=60), rsv.evolve_opts(10, reorth=2)]:
         with pytest.raises(rsv.RsvError) as e:
             rsv.rsv_evolve(reg, pl, opts)
         assert e.value.code == rsv.RSV_EINVAL
