@@ -22,7 +22,8 @@
 namespace rsv {
 namespace {
 
-constexpr int kThreads = 512;
+constexpr int kThreadBits = 9;
+constexpr int kThreads = 1 << kThreadBits;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxBessel = 512;
 
@@ -47,7 +48,7 @@ struct Shared {
   double alpha[kMaxKrylov + 1], beta[kMaxKrylov + 1], scale[kMaxKrylov + 1];
   double yre[kMaxKrylov], yim[kMaxKrylov];
   double bessel[kMaxBessel + 1];
-  double up_re[kMaxAtoms], up_im[kMaxAtoms], dn_re[kMaxAtoms], dn_im[kMaxAtoms], dl[kMaxAtoms];
+  double dl[kMaxAtoms];  // detuning of bit p at the current step
   double red[kWaves];
   double est, cheb_c, cheb_r;
   int cheb_k;
@@ -185,6 +186,8 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
   constexpr int AMAX = PackGeo<R>::A;
   __shared__ C tile[kThreads * AMAX];  // the current Krylov vector u (each thread owns tile[e])
   __shared__ Shared sh;
+  __shared__ R cf[4 * kMaxPackBits];   // couplings of bit p: <1|h|0> re, im, <0|h|1> re, im
+  __shared__ R dg[kThreads * AMAX];    // diagonal of H_k
   const PackedJob& jb = jobs[blockIdx.x];
   const int n = jb.n;
   const uint32_t dim = 1u << n;
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
   auto mine = [&](int s) { return s < A && tid + kThreads * s < dim; };
 
   C z[AMAX];  // H u of the newest Krylov vector
-  R d[AMAX];  // diagonal of H_k
+  // the diagonal of H_k lives in LDS (dg[e], written and read by the thread that owns e)
 #pragma unroll
   for (int s = 0; s < AMAX; ++s) {
     z[s] = C{0, 0};
@@ -209,25 +212,57 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
   const double tau = jb.dt_ns * 1e-3;
 
   // z = H u with u in the tile; returns Re<u, z>
+  // element s of this thread is e = tid | s << 9: bits below 9 are the thread's, the others
+  // are known at compile time in the unrolled loops
   auto apply_h = [&]() -> double {
     __syncthreads();
     double dot = 0.0;
+    if (!jb.per_site) {
+      // one coupling for every atom: sum the neighbours with the bit set and all of them,
+      // then apply <1|h|0> and <0|h|1> once
+      const R ur = cf[0], ui = cf[1], dr = cf[2], di = cf[3];
 #pragma unroll
-    for (int s = 0; s < AMAX; ++s) {
-      const uint32_t e = tid + kThreads * s;
-      if (mine(s)) {
-        const C us = tile[e];
-        C acc = {d[s] * us.x, d[s] * us.y};
-        for (int p = 0; p < n; ++p) {
-          const C nb = tile[e ^ (1u << p)];
-          const bool bit = (e >> p) & 1u;
-          const R cr = (R)(bit ? sh.up_re[p] : sh.dn_re[p]);
-          const R ci = (R)(bit ? sh.up_im[p] : sh.dn_im[p]);
-          acc.x += cr * nb.x - ci * nb.y;
-          acc.y += cr * nb.y + ci * nb.x;
+      for (int s = 0; s < AMAX; ++s) {
+        const uint32_t e = tid | ((uint32_t)s << kThreadBits);
+        if (mine(s)) {
+          const C us = tile[e];
+          C all = {0, 0}, one = {0, 0};
+          for (int p = 0; p < n; ++p) {
+            const C nb = tile[e ^ (1u << p)];
+            all.x += nb.x;
+            all.y += nb.y;
+            if ((e >> p) & 1u) {
+              one.x += nb.x;
+              one.y += nb.y;
+            }
+          }
+          const C zr = {all.x - one.x, all.y - one.y};
+          C acc;
+          const R de = dg[e];
+          acc.x = de * us.x + (ur * one.x - ui * one.y) + (dr * zr.x - di * zr.y);
+          acc.y = de * us.y + (ur * one.y + ui * one.x) + (dr * zr.y + di * zr.x);
+          z[s] = acc;
+          dot += (double)us.x * (double)acc.x + (double)us.y * (double)acc.y;
         }
-        z[s] = acc;
-        dot += (double)us.x * (double)acc.x + (double)us.y * (double)acc.y;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < AMAX; ++s) {
+        const uint32_t e = tid | ((uint32_t)s << kThreadBits);
+        if (mine(s)) {
+          const C us = tile[e];
+          const R de = dg[e];
+          C acc = {de * us.x, de * us.y};
+          for (int p = 0; p < n; ++p) {
+            const C nb = tile[e ^ (1u << p)];
+            const int o = 4 * p + (((e >> p) & 1u) ? 0 : 2);
+            const R cr = cf[o], ci = cf[o + 1];
+            acc.x += cr * nb.x - ci * nb.y;
+            acc.y += cr * nb.y + ci * nb.x;
+          }
+          z[s] = acc;
+          dot += (double)us.x * (double)acc.x + (double)us.y * (double)acc.y;
+        }
       }
     }
     return wg_sum(dot, sh.red);  // its barriers end every read of the tile
@@ -250,10 +285,10 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
       const double om = midpoint(jb.omega + off, step, jb.dt_ns);
       const double de = midpoint(jb.delta + off, step, jb.dt_ns);
       const double ph = jb.phi ? midpoint(jb.phi + off, step, jb.dt_ns) : 0.0;
-      sh.up_re[tid] = 0.5 * om * cos(ph);
-      sh.up_im[tid] = -0.5 * om * sin(ph);
-      sh.dn_re[tid] = 0.5 * om * cos(ph);
-      sh.dn_im[tid] = 0.5 * om * sin(ph);
+      cf[4 * tid] = (R)(0.5 * om * cos(ph));
+      cf[4 * tid + 1] = (R)(-0.5 * om * sin(ph));
+      cf[4 * tid + 2] = (R)(0.5 * om * cos(ph));
+      cf[4 * tid + 3] = (R)(0.5 * om * sin(ph));
       sh.dl[tid] = de;
     }
     __syncthreads();
@@ -266,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void packed_evolve_kernel(const PackedJob
         for (int p = 0; p < n; ++p)
           if ((e >> p) & 1u) v -= sh.dl[p];
       }
-      d[s] = (R)v;
+      dg[e] = (R)v;
     }
 
     double remaining = tau;
