@@ -92,7 +92,20 @@ struct PassArgs {
   Cx<R>* out;
   double* part_dot;  // optional: per-workgroup Re<u, out>
   uint32_t nblk;
+  int streaming;     // vectors far larger than the caches: stores bypass them
 };
+
+// Store of one amplitude; streaming stores skip the caches (nothing written by a pass is
+// read again before the whole vector has streamed through).
+template <class T>
+__device__ __forceinline__ void put(T* p, const T& v, int streaming) {
+  if (streaming) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+  } else {
+    *p = v;
+  }
+}
 
 template <class R>
 __device__ __forceinline__ double input_coef1(const PassArgs<R>& p) {
@@ -232,7 +245,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
   if (p.u_out) {
 #pragma unroll
     for (int s = 0; s < A; ++s) {
-      p.u_out[base + tid + NT * s] = v[s];
+      put(&p.u_out[base + tid + NT * s], v[s], p.streaming);
       nrm = norm_add(nrm, (double)v[s].x, (double)v[s].y);
     }
   }
@@ -265,7 +278,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
 #pragma unroll
       for (int q = 0; q < RB; ++q) cmad<R>(acc[s], c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
       if (p.tb) cadd<R>(acc[s], tv[s]);
-      p.out[base + tid + NT * s] = acc[s];
+      put(&p.out[base + tid + NT * s], acc[s], p.streaming);
       dot += (double)v[s].x * (double)acc[s].x + (double)v[s].y * (double)acc[s].y;
     }
   } else {
@@ -282,7 +295,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
       for (int q = 0; q < RB; ++q) ds.add(c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
       ds.finish(c, acc);
       if (p.tb) cadd<R>(acc, tv[s]);
-      p.out[b] = acc;
+      put(&p.out[b], acc, p.streaming);
       dot += (double)v[s].x * (double)acc.x + (double)v[s].y * (double)acc.y;
     }
   }
@@ -371,7 +384,7 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
   if (p.u_out) {
 #pragma unroll
     for (int s = 0; s < A; ++s) {
-      p.u_out[gi[s]] = v[s];
+      put(&p.u_out[gi[s]], v[s], p.streaming);
       nrm = norm_add(nrm, (double)v[s].x, (double)v[s].y);
     }
   }
@@ -391,7 +404,7 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
     }
     ds.finish(c, acc);
     if (p.accumulate) cadd<R>(acc, tv[s]);
-    p.tb[gi[s]] = acc;
+    put(&p.tb[gi[s]], acc, p.streaming);
   }
   if (p.part_norm) {
     const double t = wg_sum<NT>(nrm, red);
@@ -447,6 +460,7 @@ hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& 
   base.elo = dtab;
   base.etile = dtab + (size_t(1) << lbits);
   base.out = (Cx<R>*)out;
+  base.streaming = n >= 22;  // 64 MiB (complex128) / 32 MiB (complex64) vectors and up
 
   const bool first = part != kLaterPasses, later = part != kFirstPass;
   if (n < 8) {

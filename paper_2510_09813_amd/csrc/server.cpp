@@ -505,6 +505,11 @@ void lane_main(rsv_server* srv) {
       fill_error(c, rc);
       comps.push_back(c);
     }
+    // a job that failed part-way may still have work queued on the lane's stream: let it
+    // drain before its memory goes back to the arena
+    bool failed = false;
+    for (const rsv_completion& c : comps) failed |= c.status != RSV_OK;
+    if (failed && lb.stream) (void)hipStreamSynchronize(lb.stream);
     srv->arena.release(w.block, w.bytes);
     for (Job* j : w.jobs) delete j;
     {
