@@ -318,3 +318,34 @@ def test_n30_c64_capacity_and_time_reversal(ctx):
     assert 1.0 - p0 / nrm2 <= 1e-6
     del psi
     torch.cuda.empty_cache()
+
+
+def test_n29_c128_capacity_and_time_reversal(ctx):
+    """N = 29 in complex128 (8 GiB per vector, the largest complex128 register that fits):
+    two quench steps of the 29-atom triangular pattern forward, then back with Omega, delta
+    and C negated, to |0...0> within the complex128 tolerance."""
+    import torch
+    torch.cuda.empty_cache()
+    w = wl.triangular30(n_atoms=29, precision="c128")
+    kmax = 16
+    need = rsv.rsv_workspace_bytes(29, kmax, "c128")
+    free, _ = torch.cuda.mem_get_info()
+    assert need < free, (need, free)
+    reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c128")
+    psi = torch.zeros(1 << 29, dtype=torch.complex128, device="cuda:0")
+    psi[0] = 1
+    st = rsv.rsv_evolve_device(reg, rsv.PulseArrays(w.omega, w.delta),
+                               rsv.evolve_opts(w.dt_ns, 1e-10, kmax, 12, 0, 2), psi)
+    rsv.rsv_register_destroy(reg)
+    assert st.steps == 2 and abs(st.norm_final - 1.0) < 1e-10
+    K = w.n_steps
+    reg = rsv.rsv_register_create(ctx, w.xyz, -w.c6, "c128")
+    back = rsv.PulseArrays(-w.omega[::-1].copy(), -w.delta[::-1].copy())
+    rsv.rsv_evolve_device(reg, back, rsv.evolve_opts(w.dt_ns, 1e-10, kmax, 12, K - 2, 2), psi)
+    rsv.rsv_register_destroy(reg)
+    p0 = float(abs(psi[0].item()) ** 2)
+    nrm2 = float(torch.linalg.vector_norm(psi).item() ** 2)
+    assert 1.0 - p0 / nrm2 <= 1e-10
+    del psi
+    torch.cuda.empty_cache()
+
