@@ -217,15 +217,33 @@ def small_job_leg(rsv, wl, ctx, n_jobs, lanes):
     return out
 
 
+# Sources the H psi kernels are compiled from; their digest ignores comments and blank lines.
+HPSI_SOURCES = ("hpsi.hip", "common.cuh", "rsv_internal.h")
+
+
+def hpsi_code_digest(read=None):
+    """sha256 over the H psi kernel sources with // comments and blank lines removed;
+    read(name) -> text (default: the working tree)."""
+    if read is None:
+        def read(name):
+            return open(os.path.join(ROOT, "paper_2510_09813_amd", "csrc", name)).read()
+    h = hashlib.sha256()
+    for name in HPSI_SOURCES:
+        for line in read(name).splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()
+
+
 def pmc_traffic(prec):
     """HBM bytes per H psi application from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    was taken on the current kernel code."""
     path = os.path.join(ROOT, "profiles", f"hpsi_random27_{prec}_traffic.json")
-    src = os.path.join(ROOT, "paper_2510_09813_amd", "csrc", "hpsi.hip")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("hpsi_src_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if rec.get("hpsi_code_sha256") != hpsi_code_digest():
         return None
     return rec.get("bytes_per_application")
 

@@ -12,10 +12,11 @@
 //    two small FP64 tables (a 2^L table of the low-bit pairs, read from L2, and per tile the
 //    high-bit pairs and the low-high couplings), so no 2^n diagonal is read from HBM, plus
 //    the detuning from the bit pattern; and it adds the high-pass result t.
-//  * high passes (n > L): a tile of 2^r contiguous amplitudes (a run of 64 or 128 bytes)
-//    times the combinations of up to H - r high bits flips those high bits.  The first
-//    high pass writes t, later ones accumulate into it.  A last pass with few bits left
-//    widens its contiguous run instead.
+//  * high passes (n > L): a tile of 2^r contiguous amplitudes (r = 3..6: runs of 64 B to
+//    1 KiB) times the combinations of up to H - r high bits flips those high bits.  The
+//    first high pass writes t, later ones accumulate into it.  The passes are as few as the
+//    shortest run allows; the tile bits left over lengthen the runs, the forming pass's
+//    first.  For vectors far beyond the caches the passes store with streaming stores.
 //
 // The first pass of a sweep may *form* its input from up to three stored vectors,
 //   u = a0 x0 + (a1 + c * dot[0]) x1 + a2 x2,
