@@ -313,6 +313,8 @@ void register_destroy(rsv_register* reg, hipStream_t stream) {
   if (reg->d_hbuf) reg->alloc->release(reg->d_hbuf, vec_bytes(reg->n, reg->prec));
   if (reg->d_ub) reg->alloc->release(reg->d_ub, reg->bytes);
   if (reg->own_h_scal && reg->h_scal) (void)hipHostFree(reg->h_scal);
+  if (reg->have_ev)
+    for (hipEvent_t e : reg->ev) (void)hipEventDestroy(e);
   delete reg;
 }
 
@@ -358,12 +360,22 @@ struct Lanczos {
   std::vector<double> work;
 };
 
+// Device scalar slots [first_slot, first_slot + count) through the same slots of h_scal.
 int fetch_scalars(Lanczos& L, int first_slot, int count, double* out) {
-  double* h = L.reg->h_scal;
+  double* h = L.reg->h_scal + first_slot;
   HIP_TRY(hipMemcpyAsync(h, L.reg->ws.dscal + first_slot, count * sizeof(double),
                          hipMemcpyDeviceToHost, L.s));
   HIP_TRY(hipStreamSynchronize(L.s));
   for (int i = 0; i < count; ++i) out[i] = h[i];
+  return RSV_OK;
+}
+
+// Events marking the per-iteration scalar copies, created once per register.
+int ensure_events(rsv_register* reg) {
+  if (reg->have_ev) return RSV_OK;
+  for (int k = 0; k <= kMaxKrylov; ++k)
+    HIP_TRY(hipEventCreateWithFlags(&reg->ev[k], hipEventDisableTiming));
+  reg->have_ev = true;
   return RSV_OK;
 }
 
@@ -431,6 +443,10 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
   const int64_t np_norm = sweep_norm_partials(prec, n), np_dot = sweep_dot_partials(prec, n);
   const bool single = sweep_passes(prec, n) == 1;
   const double hbytes = (double)(size_t(1) << n) * (prec == kC128 ? 40.0 : 20.0);
+  // below 256 MiB per vector an iteration's kernels are short and the host round trip would
+  // leave the device idle: queue one iteration ahead (re-orthogonalisation needs the host)
+  const bool ahead = !reorth && vec_bytes(n, prec) < (size_t(256) << 20);
+  RSV_TRY(ensure_events(reg));
   double remaining = tau;
   while (remaining > 0.0) {
     const double nrm = std::sqrt(L.norm2);
@@ -447,20 +463,52 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
     }
     int m = 0;
     double sub = remaining;
-    for (int k = 1; k <= kmax; ++k) {
-      const double sk1 = L.scale[k - 1];
-      const SweepIn in{ws.z, ws.basis[k - 1], k >= 2 ? ws.basis[k - 2] : nullptr, sk1, 0.0,
-                       k >= 2 ? -L.scale[k - 2] / sk1 : 0.0, ws.dscal + (2 * (k - 1) + 1),
-                       -sk1 * sk1 * sk1};
+    // device address of |u_k|^2 (|psi|^2 for k = 0): the forming pass takes s_k from it
+    auto dev_norm = [&](int k) { return ws.dscal + (k == 0 ? kNormSlot : 2 * k); };
+    // u_k from z_{k-1}, u_{k-1}, u_{k-2} with device-side coefficients, |u_k|^2, and the
+    // copy of (<u_{k-1}, z_{k-1}>, |u_k|^2) to the pinned host scalars, marked by ev[k]
+    auto form = [&](int k) -> int {
+      SweepIn in{ws.z, ws.basis[k - 1], k >= 2 ? ws.basis[k - 2] : nullptr, 0.0, 0.0, 0.0,
+                 ws.dscal + (2 * (k - 1) + 1), 0.0};
+      in.nrm1 = dev_norm(k - 1);
+      in.nrm2 = k >= 2 ? dev_norm(k - 2) : nullptr;
       const SweepOut so{ws.basis[k], ws.pnorm, ws.pdot};
       // single-pass sizes compute z_k in the same pass; otherwise only the forming pass
       HIP_TRY(hpsi_sweep(prec, n, c, reg->d_dtab, in, ws.z, ws.t, so, kFirstPass, L.s));
       HIP_TRY(finalize_sum(ws.pnorm, np_norm, ws.dscal + 2 * k, L.s));
       if (single) HIP_TRY(finalize_sum(ws.pdot, np_dot, ws.dscal + 2 * k + 1, L.s));
-      double ab[2];  // <u_{k-1}, z_{k-1}>, |u_k|^2
-      RSV_TRY(fetch_scalars(L, 2 * k - 1, 2, ab));
+      HIP_TRY(hipMemcpyAsync(reg->h_scal + 2 * k - 1, ws.dscal + 2 * k - 1, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, L.s));
+      HIP_TRY(hipEventRecord(reg->ev[k], L.s));
+      return RSV_OK;
+    };
+    // z_k = H u_k: the remaining passes, or all of them when u_k was re-orthogonalised
+    // after the forming pass
+    auto later = [&](int k) -> int {
+      if (single && !reorth) return RSV_OK;
+      const SweepIn in2{ws.basis[k], nullptr, nullptr, 1.0, 0.0, 0.0, nullptr, 0.0};
+      const SweepOut so2{nullptr, nullptr, ws.pdot};
+      HIP_TRY(hpsi_sweep(prec, n, c, reg->d_dtab, in2, ws.z, ws.t, so2,
+                         reorth ? kAllPasses : kLaterPasses, L.s));
+      HIP_TRY(finalize_sum(ws.pdot, np_dot, ws.dscal + 2 * k + 1, L.s));
+      return RSV_OK;
+    };
+    RSV_TRY(form(1));
+    for (int k = 1; k <= kmax; ++k) {
+      // run ahead: queue iteration k+1 before reading iteration k's scalars, so the device
+      // never waits for the host (one iteration is wasted when k converges)
+      const bool speculate = ahead && k < kmax;
+      if (speculate) {
+        RSV_TRY(later(k));
+        RSV_TRY(form(k + 1));
+        L.st->krylov_iters += 1;
+        L.st->bytes_hpsi += hbytes;
+      }
+      HIP_TRY(hipEventSynchronize(reg->ev[k]));
+      double ab[2] = {reg->h_scal[2 * k - 1], reg->h_scal[2 * k]};  // <u_{k-1}, z_{k-1}>, |u_k|^2
       if (!std::isfinite(ab[0]) || !std::isfinite(ab[1]))
         return fail(RSV_ENUMERIC, "Lanczos coefficient not finite at iteration %d", k);
+      const double sk1 = L.scale[k - 1];
       L.alpha[k - 1] = sk1 * sk1 * ab[0];
       if (reorth) {
         RSV_TRY(reorthogonalise(L, k, &ab[1]));
@@ -496,17 +544,12 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
       }
       L.beta[k - 1] = bk;
       L.scale[k] = 1.0 / bk;
-      if (!single || reorth) {
-        // z_k = H u_k: the remaining passes, or all of them when u_k was re-orthogonalised
-        // after the forming pass
-        const SweepIn in2{ws.basis[k], nullptr, nullptr, 1.0, 0.0, 0.0, nullptr, 0.0};
-        const SweepOut so2{nullptr, nullptr, ws.pdot};
-        HIP_TRY(hpsi_sweep(prec, n, c, reg->d_dtab, in2, ws.z, ws.t, so2,
-                           reorth ? kAllPasses : kLaterPasses, L.s));
-        HIP_TRY(finalize_sum(ws.pdot, np_dot, ws.dscal + 2 * k + 1, L.s));
+      if (!speculate) {
+        RSV_TRY(later(k));
+        RSV_TRY(form(k + 1));
+        L.st->krylov_iters += 1;
+        L.st->bytes_hpsi += hbytes;
       }
-      L.st->krylov_iters += 1;
-      L.st->bytes_hpsi += hbytes;
     }
     L.st->krylov_max = std::max<int64_t>(L.st->krylov_max, m);
     if (tridiag_expm(m, L.alpha, L.beta, sub, L.yre, L.yim, L.work.data()) != 0)

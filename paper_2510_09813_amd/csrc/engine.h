@@ -115,6 +115,8 @@ struct rsv_register {
   rsv::Workspace ws;
   double* h_scal = nullptr;  // pinned host scalars of the per-iteration exchange
   bool own_h_scal = false;
+  hipEvent_t ev[rsv::kMaxKrylov + 1] = {};  // iteration k's scalars have reached h_scal
+  bool have_ev = false;
 };
 
 struct rsv_result {

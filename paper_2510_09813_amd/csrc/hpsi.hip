@@ -82,6 +82,8 @@ struct PassArgs {
   double a0, a1, a2;
   const double* dot;  // optional: a1 += dot_coef * dot[0]
   double dot_coef;
+  const double* nrm1;  // optional: coefficients from device norms (see SweepIn)
+  const double* nrm2;
   Cx<R>* u_out;       // optional: store the formed input
   double* part_norm;  // optional: per-workgroup |u|^2
   // high pass
@@ -108,26 +110,36 @@ __device__ __forceinline__ void put(T* p, const T& v, int streaming) {
   }
 }
 
+// Coefficients of the formed input u = a0 x0 + b1 x1 + a2 x2.
+struct Coefs {
+  double a0, b1, a2;
+};
+
 template <class R>
-__device__ __forceinline__ double input_coef1(const PassArgs<R>& p) {
-  return p.dot ? p.a1 + p.dot_coef * p.dot[0] : p.a1;
+__device__ __forceinline__ Coefs input_coefs(const PassArgs<R>& p) {
+  if (p.nrm1) {  // s_{k-1}, s_{k-2} from the norms of the stored vectors
+    const double s1 = 1.0 / sqrt(p.nrm1[0]);
+    const double s2 = p.nrm2 ? 1.0 / sqrt(p.nrm2[0]) : 0.0;
+    return Coefs{s1, -s1 * s1 * s1 * p.dot[0], -s2 / s1};
+  }
+  return Coefs{p.a0, p.dot ? p.a1 + p.dot_coef * p.dot[0] : p.a1, p.a2};
 }
 
 // u = a0 x0[i] + b1 x1[i] + a2 x2[i] in FP64, rounded once to the storage precision.
 template <class R>
-__device__ __forceinline__ Cx<R> form(const PassArgs<R>& p, double b1, size_t i) {
+__device__ __forceinline__ Cx<R> form(const PassArgs<R>& p, const Coefs& co, size_t i) {
   const Cx<R> v0 = p.x0[i];
-  if (!p.x1 && !p.x2 && p.a0 == 1.0) return v0;
-  double re = p.a0 * (double)v0.x, im = p.a0 * (double)v0.y;
+  if (!p.x1 && !p.x2 && co.a0 == 1.0) return v0;
+  double re = co.a0 * (double)v0.x, im = co.a0 * (double)v0.y;
   if (p.x1) {
     const Cx<R> v1 = p.x1[i];
-    re += b1 * (double)v1.x;
-    im += b1 * (double)v1.y;
+    re += co.b1 * (double)v1.x;
+    im += co.b1 * (double)v1.y;
   }
   if (p.x2) {
     const Cx<R> v2 = p.x2[i];
-    re += p.a2 * (double)v2.x;
-    im += p.a2 * (double)v2.y;
+    re += co.a2 * (double)v2.x;
+    im += co.a2 * (double)v2.y;
   }
   Cx<R> r;
   r.x = (R)re;
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
   const uint32_t base = blk << LB;
   if (CM == kCoefSite) build_delta_lut<R>(c, lut);
 
-  const double b1 = input_coef1(p);
+  const Coefs co = input_coefs(p);
   C v[A], tv[A];
   R dg[A];
   double nrm = 0.0;
@@ -233,7 +245,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
 #pragma unroll
   for (int s = 0; s < A; ++s) {
     const uint32_t e = tid + NT * s;
-    v[s] = form<R>(p, b1, base + e);
+    v[s] = form<R>(p, co, base + e);
     tv[s] = p.tb ? p.tb[base + e] : C{0, 0};
     double es = eth;
 #pragma unroll
@@ -324,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void hpsi_small_kernel(const StepCoef c, co
   C v = {0, 0};
   double nrm = 0.0, dot = 0.0;
   if (tid < dim) {
-    v = form<R>(p, input_coef1(p), tid);
+    v = form<R>(p, input_coefs(p), tid);
     tile[tid] = v;
     if (p.u_out) {
       p.u_out[tid] = v;
@@ -368,7 +380,7 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
   const int gap = p.a - RL;  // outside bits between the contiguous run and the tile's high bits
   const uint32_t obase = ((blk & ((1u << gap) - 1u)) << RL) | ((blk >> gap) << (p.a + G));
 
-  const double b1 = input_coef1(p);
+  const Coefs co = input_coefs(p);
   C v[A], tv[A];
   uint32_t gi[A];
   double nrm = 0.0;
@@ -377,7 +389,7 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
   for (int s = 0; s < A; ++s) {
     const uint32_t e = tid + NT * s;
     gi[s] = obase | (e & ((1u << RL) - 1u)) | ((e >> RL) << p.a);
-    v[s] = form<R>(p, b1, gi[s]);
+    v[s] = form<R>(p, co, gi[s]);
     tv[s] = p.accumulate ? p.tb[gi[s]] : C{0, 0};
   }
 #pragma unroll
@@ -457,11 +469,14 @@ hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& 
   base.a2 = in.a2;
   base.dot = in.dot;
   base.dot_coef = in.dot_coef;
+  base.nrm1 = in.nrm1;
+  base.nrm2 = in.nrm2;
   const int lbits = make_tile_plan(sizeof(R) == 8 ? kC128 : kC64, n).lo_bits;
   base.elo = dtab;
   base.etile = dtab + (size_t(1) << lbits);
   base.out = (Cx<R>*)out;
-  base.streaming = n >= 22;  // 64 MiB (complex128) / 32 MiB (complex64) vectors and up
+  // vectors of 256 MiB and more (the size of the last-level cache) stream past the caches
+  base.streaming = (size_t(1) << n) * sizeof(Cx<R>) >= (size_t(256) << 20);
 
   const bool first = part != kLaterPasses, later = part != kFirstPass;
   if (n < 8) {
@@ -475,7 +490,7 @@ hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& 
   }
   const TilePlan plan = make_tile_plan(sizeof(R) == 8 ? kC128 : kC64, n);
   // the formed input, once stored, is the plain input of every later pass
-  const bool forming = in.x1 || in.x2 || in.a0 != 1.0 || in.dot;
+  const bool forming = in.x1 || in.x2 || in.a0 != 1.0 || in.dot || in.nrm1;
   if (forming && plan.n_hi_passes > 0 && !so.u_out) return hipErrorInvalidValue;
   const Cx<R>* stored = so.u_out ? (const Cx<R>*)so.u_out : (const Cx<R>*)in.x0;
   for (int i = 0; i < plan.n_hi_passes; ++i) {
@@ -486,6 +501,7 @@ hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& 
       p.x1 = p.x2 = nullptr;
       p.a0 = 1.0;
       p.dot = nullptr;
+      p.nrm1 = p.nrm2 = nullptr;
     } else {
       p.u_out = (Cx<R>*)so.u_out;
       p.part_norm = so.part_norm;
@@ -505,6 +521,7 @@ hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& 
     p.x1 = p.x2 = nullptr;
     p.a0 = 1.0;
     p.dot = nullptr;
+    p.nrm1 = p.nrm2 = nullptr;
     p.tb = (Cx<R>*)tbuf;
   } else {
     p.u_out = (Cx<R>*)so.u_out;

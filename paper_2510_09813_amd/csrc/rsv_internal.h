@@ -63,7 +63,10 @@ struct TilePlan {
 TilePlan make_tile_plan(int prec, int n);
 
 // Input of one H sweep: u = a0 x0 + (a1 + dot_coef * dot[0]) x1 + a2 x2 (x1, x2, dot may
-// be null).  With only x0 and a0 = 1 the sweep applies H to a stored vector.
+// be null).  With only x0 and a0 = 1 the sweep applies H to a stored vector.  When nrm1 is
+// set the Lanczos coefficients come from device memory instead: with s1 = 1/sqrt(nrm1[0])
+// and s2 = 1/sqrt(nrm2[0]) (0 without nrm2), a0 = s1, the x1 coefficient is
+// -s1^3 dot[0] and a2 = -s2/s1 -- so a sweep can be queued before the host has read them.
 struct SweepIn {
   const void* x0;
   const void* x1;
@@ -71,6 +74,8 @@ struct SweepIn {
   double a0, a1, a2;
   const double* dot;
   double dot_coef;
+  const double* nrm1 = nullptr;
+  const double* nrm2 = nullptr;
 };
 // Optional outputs: u_out stores the formed u (required when the sweep forms u and has
 // more than one pass); part_norm / part_dot receive per-workgroup FP64 partial sums of |u|^2
