@@ -11,7 +11,10 @@
 //    thread's registers.  This pass applies the diagonal: the interaction energy E_b from
 //    two small FP64 tables (a 2^L table of the low-bit pairs, read from L2, and per tile the
 //    high-bit pairs and the low-high couplings), so no 2^n diagonal is read from HBM, plus
-//    the detuning from the bit pattern; and it adds the high-pass result t.
+//    the detuning from the bit pattern; and it adds the high-pass result t.  Where that
+//    saves a high pass, it also flips up to 7 bits above its tile, reading those neighbours
+//    from the adjacent tiles in global memory (mostly cache hits): n = 22..28 complex128
+//    and 23..29 complex64 then need one high pass.
 //  * high passes (n > L): a tile of 2^r contiguous amplitudes (r = 3..6: runs of 64 B to
 //    1 KiB) times the combinations of up to H - r high bits flips those high bits.  The
 //    first high pass writes t, later ones accumulate into it.  The passes are as few as the
@@ -215,8 +218,19 @@ struct DriveSum {
 };
 
 // ----------------------------------------------------------------------------- low pass
-template <class R, int LB, int NT, int CM>
-__global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const PassArgs<R> p) {
+// E > 0: the pass also flips bits LB .. LB + E - 1, whose neighbours lie in E other tiles
+// of the same aligned group of 2^E tiles.  Those are read straight from global memory (the
+// input is then a stored vector): a group's tiles run back to back on one XCD, so most of
+// these reads are served by its L2 or the last-level cache rather than HBM.
+template <class R, int LB, int NT, int CM, int E>
+constexpr int lo_min_waves() {
+  // two complex128 workgroups per CU (4 waves per SIMD) where the registers allow it without
+  // spilling: the extension's loads would otherwise push the global-drive forms past 128
+  return sizeof(R) == 8 && LB == 12 && NT == 512 && CM != kCoefSite ? 4 : 1;
+}
+
+template <class R, int LB, int NT, int CM, int E>
+__global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_lo_kernel(const StepCoef c, const PassArgs<R> p) {
   using C = Cx<R>;
   constexpr int TB = ilog2(NT);      // thread-index bits
   static_assert(LB >= TB, "tile smaller than the workgroup");
@@ -242,16 +256,29 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
 #pragma unroll
   for (int q = 0; q < TB; ++q)
     if ((tid >> q) & 1u) eth += et[1 + q];
+  // (the input test sits outside the loops, so that the loads of a stored input are issued
+  // back to back rather than one branch at a time)
+  if (!p.x1 && !p.x2 && co.a0 == 1.0) {
+#pragma unroll
+    for (int s = 0; s < A; ++s) v[s] = p.x0[base + tid + NT * s];
+  } else {
+#pragma unroll
+    for (int s = 0; s < A; ++s) v[s] = form<R>(p, co, base + tid + NT * s);
+  }
+  if (p.tb) {
+#pragma unroll
+    for (int s = 0; s < A; ++s) tv[s] = p.tb[base + tid + NT * s];
+  } else {
+#pragma unroll
+    for (int s = 0; s < A; ++s) tv[s] = C{0, 0};
+  }
 #pragma unroll
   for (int s = 0; s < A; ++s) {
-    const uint32_t e = tid + NT * s;
-    v[s] = form<R>(p, co, base + e);
-    tv[s] = p.tb ? p.tb[base + e] : C{0, 0};
     double es = eth;
 #pragma unroll
     for (int q = 0; q < RB; ++q)
       if ((s >> q) & 1) es += et[1 + TB + q];
-    dg[s] = (R)(p.elo[e] + es);
+    dg[s] = (R)(p.elo[tid + NT * s] + es);
   }
 #pragma unroll
   for (int s = 0; s < A; ++s) tile[tid + NT * s] = v[s];
@@ -262,7 +289,35 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
       nrm = norm_add(nrm, (double)v[s].x, (double)v[s].y);
     }
   }
+  // flips of the bits above the tile: bit LB + j of every amplitude here is bit j of the tile
+  // index, so its coefficient is the same for the whole workgroup; the terms join the
+  // high-pass partial (requested before the barrier, like the tile).  The loads of one bit
+  // are issued together into their own registers before any is used: written as one
+  // load-and-add per amplitude, the compiler issues them one at a time at this register
+  // budget, which made the pass about 30 % slower.
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const bool bit = (blk >> j) & 1u;
+    const int q = CM == kCoefSite ? LB + j : 0;
+    const R cr = (R)(bit ? c.up_re[q] : c.dn_re[q]);
+    const R ci = (R)(bit ? c.up_im[q] : c.dn_im[q]);
+    const uint32_t nbase = (blk ^ (1u << j)) << LB;
+    C nb[A];
+#pragma unroll
+    for (int s = 0; s < A; ++s) nb[s] = p.x0[nbase + tid + NT * s];
+#pragma unroll
+    for (int s = 0; s < A; ++s) {
+      tv[s].x += cr * nb[s].x - ci * nb[s].y;
+      tv[s].y += cr * nb[s].y + ci * nb[s].x;
+    }
+  }
   __syncthreads();
+  if constexpr (E > 0) {
+    // the thread's own amplitudes come back from the tile: not holding them in registers
+    // across the barrier leaves room for the neighbour loads to be in flight together
+#pragma unroll
+    for (int s = 0; s < A; ++s) v[s] = tile[tid + NT * s];
+  }
 
   double dot = 0.0;
   if constexpr (CM == kCoefSite) {
@@ -290,7 +345,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
     for (int s = 0; s < A; ++s) {
 #pragma unroll
       for (int q = 0; q < RB; ++q) cmad<R>(acc[s], c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
-      if (p.tb) cadd<R>(acc[s], tv[s]);
+      if (E > 0 || p.tb) cadd<R>(acc[s], tv[s]);
       put(&p.out[base + tid + NT * s], acc[s], p.streaming);
       dot += (double)v[s].x * (double)acc[s].x + (double)v[s].y * (double)acc[s].y;
     }
@@ -307,7 +362,7 @@ __global__ __launch_bounds__(NT) void hpsi_lo_kernel(const StepCoef c, const Pas
 #pragma unroll
       for (int q = 0; q < RB; ++q) ds.add(c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
       ds.finish(c, acc);
-      if (p.tb) cadd<R>(acc, tv[s]);
+      if (E > 0 || p.tb) cadd<R>(acc, tv[s]);
       put(&p.out[b], acc, p.streaming);
       dot += (double)v[s].x * (double)acc.x + (double)v[s].y * (double)acc.y;
     }
@@ -425,15 +480,27 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
   }
 }
 
-template <class R, int LB, int CM>
+template <class R, int LB, int CM, int E = 0>
 void launch_lo(const StepCoef& c, PassArgs<R> p, int n, hipStream_t s) {
   constexpr int NT = lo_threads<R, CM>() < (1 << LB) ? lo_threads<R, CM>() : (1 << LB);
   p.nblk = 1u << (n - LB);
-  hipLaunchKernelGGL((hpsi_lo_kernel<R, LB, NT, CM>), dim3(p.nblk), dim3(NT), 0, s, c, p);
+  hipLaunchKernelGGL((hpsi_lo_kernel<R, LB, NT, CM, E>), dim3(p.nblk), dim3(NT), 0, s, c, p);
 }
 
 template <class R, int CM>
-void launch_lo_any(int lb, const StepCoef& c, const PassArgs<R>& p, int n, hipStream_t s) {
+void launch_lo_any(int lb, int ext, const StepCoef& c, const PassArgs<R>& p, int n, hipStream_t s) {
+  constexpr int L = Geo<R>::L;
+  static_assert(kMaxLoExt == 7, "launch_lo_any instantiates extensions 1..7");
+  switch (ext) {  // extensions are planned on full-size tiles only
+    case 0: break;
+    case 1: launch_lo<R, L, CM, 1>(c, p, n, s); return;
+    case 2: launch_lo<R, L, CM, 2>(c, p, n, s); return;
+    case 3: launch_lo<R, L, CM, 3>(c, p, n, s); return;
+    case 4: launch_lo<R, L, CM, 4>(c, p, n, s); return;
+    case 5: launch_lo<R, L, CM, 5>(c, p, n, s); return;
+    case 6: launch_lo<R, L, CM, 6>(c, p, n, s); return;
+    default: launch_lo<R, L, CM, 7>(c, p, n, s); return;
+  }
   switch (lb) {
     case 8: launch_lo<R, 8, CM>(c, p, n, s); break;
     case 9: launch_lo<R, 9, CM>(c, p, n, s); break;
@@ -528,7 +595,11 @@ hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& 
     p.part_norm = so.part_norm;
   }
   p.part_dot = so.part_dot;
-  launch_lo_any<R, CM>(plan.lo_bits, c, p, n, s);
+  // an extended low pass reads the neighbouring tiles of a stored input
+  if (plan.lo_ext > 0 && (plan.lo_bits != Geo<R>::L || plan.n_hi_passes == 0 || p.x1 || p.x2 ||
+                          p.a0 != 1.0 || p.dot || p.nrm1))
+    return hipErrorInvalidValue;
+  launch_lo_any<R, CM>(plan.lo_bits, plan.lo_ext, c, p, n, s);
   return hipGetLastError();
 }
 
@@ -553,16 +624,30 @@ TilePlan make_tile_plan(int prec, int n) {
   p.hi_bits = prec == kC128 ? Geo<double>::H : Geo<float>::H;
   p.lo_bits = n < L ? n : L;
   p.n_hi_passes = 0;
-  const int rest = n - p.lo_bits;  // bits the high passes flip
+  p.lo_ext = 0;
+  const int rest = n - p.lo_bits;  // bits above the low-pass tile
   if (rest <= 0) return p;
-  // fewest passes at the shortest run, then the spare tile bits lengthen the runs (the
-  // first, forming pass first: it moves the most bytes), up to rlw each
-  const int passes = (rest + p.hi_bits - rl - 1) / (p.hi_bits - rl);
-  int spare = passes * (p.hi_bits - rl) - rest;
-  int f0 = p.lo_bits;
+  // fewest passes at the shortest run
+  const int per = p.hi_bits - rl;
+  int passes = (rest + per - 1) / per;
+  // the low pass can flip up to kMaxLoExt more bits from the neighbouring tiles; where that
+  // saves a high pass it takes the fewest bits that do, plus one (a longer run for the
+  // high pass costs less than the one more neighbour tile)
+  if (passes >= 2) {
+    const int fewer = (rest - kMaxLoExt + per - 1) / per;
+    if (fewer < passes) {
+      const int emin = rest - fewer * per;
+      p.lo_ext = emin < kMaxLoExt ? emin + 1 : emin;
+      passes = fewer;
+    }
+  }
+  // then the spare tile bits lengthen the runs (the first, forming pass first: it moves the
+  // most bytes), up to rlw each
+  int spare = passes * per - (rest - p.lo_ext);
+  int f0 = p.lo_bits + p.lo_ext;
   for (int i = 0; i < passes; ++i) {
-    const int per = (spare + (passes - i) - 1) / (passes - i);  // spread, rounding up first
-    const int r = rl + per < rlw ? rl + per : rlw;
+    const int more = (spare + (passes - i) - 1) / (passes - i);  // spread, rounding up first
+    const int r = rl + more < rlw ? rl + more : rlw;
     spare -= r - rl;
     const int gw = p.hi_bits - r;
     const int f1 = f0 + gw < n ? f0 + gw : n;

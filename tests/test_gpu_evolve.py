@@ -144,6 +144,47 @@ def test_n27_c64_against_c128(ctx):
     assert np.abs(occ_a - occ_b).max() <= 1e-5
 
 
+@pytest.mark.parametrize("prec,n", [("c128", 24), ("c128", 26), ("c64", 25)])
+def test_steps_against_taylor_series_of_hpsi(ctx, prec, n):
+    """Sizes whose low pass also flips bits held in neighbouring tiles (22..28 atoms): two
+    Lanczos steps from a random state against exp(-i tau H_k) psi summed as a Taylor series
+    over sub-steps of norm <= 1/2, 22 terms each, with the complex128 rsv_apply_hamiltonian,
+    whose rows the H|psi> tests compare with the oracle.  This checks the driver at sizes the
+    Lanczos oracle cannot reach in seconds; the series' truncation (2e-28 per sub-step) and
+    rounding (~1e-13) are far below the bar."""
+    import torch
+    w = wl.random27(n_atoms=n)
+    first, steps = 200, 2
+    psi0 = wl.random_state(n, np.random.default_rng(n))
+    if prec == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    psi, occ, _, res = gpu_run(ctx, w, prec, psi0=psi0, first=first, steps=steps)
+    rsv.rsv_result_destroy(res)
+
+    reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c128")
+    pulses = rsv.PulseArrays(w.omega, w.delta, w.phi)
+    u = model.interaction_matrix(w.xyz, w.c6)
+    tau = w.dt_ns * 1e-3
+    x = torch.from_numpy(psi0).to("cuda:0")
+    hx = torch.empty_like(x)
+    for k in range(first, first + steps):
+        om, de, _ = model.step_parameters(n, w.omega, w.delta, w.phi, w.dt_ns, k)
+        # row-sum bound on ||H_k||: every pair energy, every detuning, every drive term
+        bound = np.abs(np.triu(u, 1)).sum() + np.abs(de).sum() + 0.5 * np.abs(om).sum()
+        m = int(np.ceil(bound * tau / 0.5))
+        h = tau / m
+        for _ in range(m):
+            term, acc = x, x.clone()
+            for j in range(1, 23):
+                rsv.rsv_apply_hamiltonian(reg, pulses, k, w.dt_ns, term, hx)
+                term = hx * (-1j * h / j)
+                acc += term
+            x = acc
+    ref = x.cpu().numpy()
+    rsv.rsv_register_destroy(reg)
+    check(psi, occ, ref, prec)
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_full_reorthogonalisation(ctx, prec):
     """reorth = 1 (every new vector orthogonalised against the whole basis): chain10 matches

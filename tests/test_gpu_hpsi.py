@@ -92,12 +92,17 @@ def test_hpsi_matches_oracle(ctx, n, per_site, phase, prec):
     rsv.rsv_register_destroy(reg)
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("per_site", [False, True])
-def test_hpsi_full_size_n27_sampled(ctx, prec, per_site):
-    """The 27-atom random register at the launch configuration the benchmark times: 2000
-    sampled rows computed one by one from the matrix elements."""
-    w = wl.random27(precision=prec)
+SAMPLED = [("c128", 27, False), ("c128", 27, True), ("c64", 27, False), ("c64", 27, True),
+           ("c128", 25, True), ("c128", 26, False), ("c128", 28, True), ("c64", 26, True),
+           ("c64", 28, False)]
+
+
+@pytest.mark.parametrize("prec,n,per_site", SAMPLED)
+def test_hpsi_full_size_sampled(ctx, prec, n, per_site):
+    """The random register at full sizes (27 atoms: the launch configuration the benchmark
+    times; 25..28: low passes that flip 4..7 bits of neighbouring tiles): 2000 sampled rows
+    computed one by one from the matrix elements."""
+    w = wl.random27(n_atoms=n, precision=prec)
     n = w.n_atoms
     rng = np.random.default_rng(42)
     om, de, ph = w.omega, w.delta, None
@@ -115,8 +120,8 @@ def test_hpsi_full_size_n27_sampled(ctx, prec, per_site):
     step = 300
     rsv.rsv_apply_hamiltonian(reg, pulses, step, w.dt_ns, d_in, d_out)
     torch.cuda.synchronize()
-    idx = np.concatenate([[0, (1 << n) - 1, 1 << 12, (1 << 12) - 1],
-                          rng.integers(0, 1 << n, 1996)])
+    idx = np.concatenate([[0, (1 << n) - 1, 1 << 12, (1 << 12) - 1, 1 << 13, (1 << 19) - 1],
+                          rng.integers(0, 1 << n, 1994)])
     u = model.interaction_matrix(w.xyz, w.c6)
     pars = model.step_parameters(n, om, de, ph, w.dt_ns, step)
     psi_h = d_in.cpu().numpy().astype(np.complex128)

@@ -1,7 +1,9 @@
 """Host logic of the H|psi> tile plans (CPU only): for every register size and both
-precisions, the high passes flip every bit above the low pass exactly once, each tile stays
-inside the index with its contiguous run below its high bits, and every pass's tiles cover
-the index space exactly once (checked element by element up to 20 atoms)."""
+precisions, the low pass (with its extension bits) and the high passes flip every bit
+exactly once, each tile stays inside the index with its contiguous run below its high bits,
+every pass's tiles cover the index space exactly once (checked element by element up to 20
+atoms), and the plan has the fewest passes that 12-bit high tiles with runs of at least
+2^3 amplitudes and an extension of at most 7 bits allow."""
 import ctypes as C
 
 import pytest
@@ -15,10 +17,11 @@ class TilePlan(C.Structure):
     _fields_ = [("n", C.c_int), ("lo_bits", C.c_int), ("hi_bits", C.c_int),
                 ("n_hi_passes", C.c_int), ("flip_lo", C.c_int * N_MAX),
                 ("flip_hi", C.c_int * N_MAX), ("tile_a", C.c_int * N_MAX),
-                ("run_bits", C.c_int * N_MAX)]
+                ("run_bits", C.c_int * N_MAX), ("lo_ext", C.c_int)]
 
 
 def plan(prec, n):
+    """rsv::make_tile_plan(prec, n) through its C++ symbol."""
     f = rsv.lib()._ZN3rsv14make_tile_planEii  # rsv::make_tile_plan(int, int), host code
     f.restype = TilePlan
     f.argtypes = [C.c_int, C.c_int]
@@ -44,7 +47,15 @@ def test_plans_partition_the_bits_and_the_index(prec):
                     for e in range(1 << p.hi_bits):
                         seen.add(obase | (e & ((1 << r) - 1)) | ((e >> r) << a))
                 assert seen == set(range(1 << n))
-        assert covered == list(range(p.lo_bits, n))
-        # the passes are as few as the shortest run allows
+        assert 0 <= p.lo_ext <= 7 and p.lo_bits + p.lo_ext <= n
+        assert covered == list(range(p.lo_bits + p.lo_ext, n))
+        # the passes are as few as the shortest run and the extension allow; the extension
+        # only where it saves a high pass, and then never below one high pass
         rest = n - p.lo_bits
-        assert p.n_hi_passes == (rest + p.hi_bits - 4) // (p.hi_bits - 3) if rest > 0 else p.n_hi_passes == 0
+        per = p.hi_bits - 3
+        plain = -(-rest // per) if rest > 0 else 0
+        fewest = -(-max(rest - 7, 0) // per)
+        if plain >= 2 and fewest < plain:
+            assert p.lo_ext > 0 and p.n_hi_passes == fewest >= 1
+        else:
+            assert p.lo_ext == 0 and p.n_hi_passes == plain
