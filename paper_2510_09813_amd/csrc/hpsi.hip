@@ -14,7 +14,7 @@
 //    the detuning from the bit pattern; and it adds the high-pass result t.  Where that
 //    saves a high pass, it also flips up to 7 bits above its tile, reading those neighbours
 //    from the adjacent tiles in global memory (mostly cache hits): n = 22..28 complex128
-//    and 23..29 complex64 then need one high pass.
+//    and 22..29 complex64 then need one high pass (complex64 on 12-bit tiles up to n = 28).
 //  * high passes (n > L): a tile of 2^r contiguous amplitudes (r = 3..6: runs of 64 B to
 //    1 KiB) times the combinations of up to H - r high bits flips those high bits.  The
 //    first high pass writes t, later ones accumulate into it.  The passes are as few as the
@@ -440,6 +440,8 @@ __global__ __launch_bounds__(NT) void hpsi_hi_kernel(const StepCoef c, const Pas
   uint32_t gi[A];
   double nrm = 0.0;
   // the partial being accumulated is requested with the state, before the barrier
+  // (one amplitude's vectors after another: issuing each vector's loads for the whole tile
+  // first measured slower here, 16 % for complex64 on the top bits)
 #pragma unroll
   for (int s = 0; s < A; ++s) {
     const uint32_t e = tid + NT * s;
@@ -487,19 +489,27 @@ void launch_lo(const StepCoef& c, PassArgs<R> p, int n, hipStream_t s) {
   hipLaunchKernelGGL((hpsi_lo_kernel<R, LB, NT, CM, E>), dim3(p.nblk), dim3(NT), 0, s, c, p);
 }
 
+template <class R, int CM, int LB>
+void launch_lo_ext(int ext, const StepCoef& c, const PassArgs<R>& p, int n, hipStream_t s) {
+  static_assert(kMaxLoExt == 7, "launch_lo_ext instantiates extensions 1..7");
+  switch (ext) {
+    case 1: launch_lo<R, LB, CM, 1>(c, p, n, s); break;
+    case 2: launch_lo<R, LB, CM, 2>(c, p, n, s); break;
+    case 3: launch_lo<R, LB, CM, 3>(c, p, n, s); break;
+    case 4: launch_lo<R, LB, CM, 4>(c, p, n, s); break;
+    case 5: launch_lo<R, LB, CM, 5>(c, p, n, s); break;
+    case 6: launch_lo<R, LB, CM, 6>(c, p, n, s); break;
+    default: launch_lo<R, LB, CM, 7>(c, p, n, s); break;
+  }
+}
+
 template <class R, int CM>
 void launch_lo_any(int lb, int ext, const StepCoef& c, const PassArgs<R>& p, int n, hipStream_t s) {
-  constexpr int L = Geo<R>::L;
-  static_assert(kMaxLoExt == 7, "launch_lo_any instantiates extensions 1..7");
-  switch (ext) {  // extensions are planned on full-size tiles only
-    case 0: break;
-    case 1: launch_lo<R, L, CM, 1>(c, p, n, s); return;
-    case 2: launch_lo<R, L, CM, 2>(c, p, n, s); return;
-    case 3: launch_lo<R, L, CM, 3>(c, p, n, s); return;
-    case 4: launch_lo<R, L, CM, 4>(c, p, n, s); return;
-    case 5: launch_lo<R, L, CM, 5>(c, p, n, s); return;
-    case 6: launch_lo<R, L, CM, 6>(c, p, n, s); return;
-    default: launch_lo<R, L, CM, 7>(c, p, n, s); return;
+  if (ext > 0) {  // extensions are planned on 12-bit tiles, and complex64's 13-bit ones
+    if constexpr (Geo<R>::L >= 13) {
+      if (lb == 13) return launch_lo_ext<R, CM, 13>(ext, c, p, n, s);
+    }
+    return launch_lo_ext<R, CM, 12>(ext, c, p, n, s);
   }
   switch (lb) {
     case 8: launch_lo<R, 8, CM>(c, p, n, s); break;
@@ -596,8 +606,8 @@ hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& 
   }
   p.part_dot = so.part_dot;
   // an extended low pass reads the neighbouring tiles of a stored input
-  if (plan.lo_ext > 0 && (plan.lo_bits != Geo<R>::L || plan.n_hi_passes == 0 || p.x1 || p.x2 ||
-                          p.a0 != 1.0 || p.dot || p.nrm1))
+  if (plan.lo_ext > 0 && ((plan.lo_bits != 12 && plan.lo_bits != Geo<R>::L) ||
+                          plan.n_hi_passes == 0 || p.x1 || p.x2 || p.a0 != 1.0 || p.dot || p.nrm1))
     return hipErrorInvalidValue;
   launch_lo_any<R, CM>(plan.lo_bits, plan.lo_ext, c, p, n, s);
   return hipGetLastError();
@@ -623,6 +633,11 @@ TilePlan make_tile_plan(int prec, int n) {
   const int rlw = prec == kC128 ? Geo<double>::RLW : Geo<float>::RLW;
   p.hi_bits = prec == kC128 ? Geo<double>::H : Geo<float>::H;
   p.lo_bits = n < L ? n : L;
+  // complex64 takes 12-bit low tiles where the extension then leaves a single high pass (22..28
+  // atoms): its 13-bit tiles hold 16 amplitudes per thread, whose registers allow one
+  // workgroup per CU, and the extended pass measured about 12 % faster on the smaller tile
+  if (prec != kC128 && n - 12 > p.hi_bits - rl && n - 12 <= p.hi_bits - rl + kMaxLoExt)
+    p.lo_bits = 12;
   p.n_hi_passes = 0;
   p.lo_ext = 0;
   const int rest = n - p.lo_bits;  // bits above the low-pass tile

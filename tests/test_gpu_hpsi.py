@@ -94,14 +94,14 @@ def test_hpsi_matches_oracle(ctx, n, per_site, phase, prec):
 
 SAMPLED = [("c128", 27, False), ("c128", 27, True), ("c64", 27, False), ("c64", 27, True),
            ("c128", 25, True), ("c128", 26, False), ("c128", 28, True), ("c64", 26, True),
-           ("c64", 28, False)]
+           ("c64", 28, False), ("c64", 29, True)]
 
 
 @pytest.mark.parametrize("prec,n,per_site", SAMPLED)
 def test_hpsi_full_size_sampled(ctx, prec, n, per_site):
     """The random register at full sizes (27 atoms: the launch configuration the benchmark
-    times; 25..28: low passes that flip 4..7 bits of neighbouring tiles): 2000 sampled rows
-    computed one by one from the matrix elements."""
+    times; 25..29: low passes that flip 4..7 bits of neighbouring tiles, on 12- and 13-bit
+    tiles): 2000 sampled rows computed one by one from the matrix elements."""
     w = wl.random27(n_atoms=n, precision=prec)
     n = w.n_atoms
     rng = np.random.default_rng(42)
