@@ -53,16 +53,16 @@ struct DotGroup {
 
 // --------------------------------------------------------------------------- H|psi>
 // Tile geometry of the H|psi> passes for a precision: the low pass's tiles cover bits
-// [0, lo_bits) and it also flips the lo_ext bits above them, reading those neighbours from
-// the adjacent tiles in global memory; high pass i covers bits
-// [tile_a, tile_a + hi_bits - run_bits) plus run_bits contiguous low bits and flips
+// [0, lo_bits) and it also flips the lo_ext bits [lo_ext_bit, lo_ext_bit + lo_ext) (the top
+// bits), reading those neighbours from other tiles in global memory; high pass i covers
+// bits [tile_a, tile_a + hi_bits - run_bits) plus run_bits contiguous low bits and flips
 // [flip_lo, flip_hi).
 constexpr int kMaxLoExt = 7;
 struct TilePlan {
   int n, lo_bits, hi_bits;
   int n_hi_passes;
   int flip_lo[kMaxAtoms], flip_hi[kMaxAtoms], tile_a[kMaxAtoms], run_bits[kMaxAtoms];
-  int lo_ext;
+  int lo_ext, lo_ext_bit;
 };
 TilePlan make_tile_plan(int prec, int n);
 

@@ -1,9 +1,9 @@
 """Host logic of the H|psi> tile plans (CPU only): for every register size and both
-precisions, the low pass (with its extension bits) and the high passes flip every bit
-exactly once, each tile stays inside the index with its contiguous run below its high bits,
-every pass's tiles cover the index space exactly once (checked element by element up to 20
-atoms), and the plan has the fewest passes that 12-bit high tiles with runs of at least
-2^3 amplitudes and an extension of at most 7 bits allow."""
+precisions, the low pass (with its extension of the top bits) and the high passes flip
+every bit exactly once, each tile stays inside the index with its contiguous run below its
+high bits, every pass's tiles cover the index space exactly once (checked element by element
+up to 20 atoms), and the plan has the fewest passes that 12-bit high tiles with runs of at
+least 2^3 amplitudes and an extension of at most 7 bits allow."""
 import ctypes as C
 
 import pytest
@@ -17,7 +17,8 @@ class TilePlan(C.Structure):
     _fields_ = [("n", C.c_int), ("lo_bits", C.c_int), ("hi_bits", C.c_int),
                 ("n_hi_passes", C.c_int), ("flip_lo", C.c_int * N_MAX),
                 ("flip_hi", C.c_int * N_MAX), ("tile_a", C.c_int * N_MAX),
-                ("run_bits", C.c_int * N_MAX), ("lo_ext", C.c_int)]
+                ("run_bits", C.c_int * N_MAX), ("lo_ext", C.c_int),
+                ("lo_ext_bit", C.c_int)]
 
 
 def plan(prec, n):
@@ -49,7 +50,10 @@ def test_plans_partition_the_bits_and_the_index(prec):
                         seen.add(obase | (e & ((1 << r) - 1)) | ((e >> r) << a))
                 assert seen == set(range(1 << n))
         assert 0 <= p.lo_ext <= 7 and p.lo_bits + p.lo_ext <= n
-        assert covered == list(range(p.lo_bits + p.lo_ext, n))
+        # the high passes flip the bits between the low tile and the extension (the top bits)
+        assert covered == list(range(p.lo_bits, n - p.lo_ext))
+        if p.lo_ext:
+            assert p.lo_ext_bit == n - p.lo_ext
         # the passes are as few as the shortest run and the extension allow; the extension
         # only where it saves a high pass, and then never below one high pass
         rest = n - p.lo_bits
