@@ -219,12 +219,6 @@ struct DriveSum {
 };
 
 // ----------------------------------------------------------------------------- low pass
-// E > 0: the pass also flips the E amplitude bits LB + g0 .. LB + g0 + E - 1 (g0 =
-// p.ext_bit; the planner puts them at the top), whose neighbours lie in E other tiles of the
-// same group of 2^E tiles (those differing in tile-index bits g0 .. g0 + E - 1).  Those are
-// read straight from global memory (the input is then a stored vector): a group's tiles take
-// consecutive positions on one XCD, so most of these reads are served by its L2 or the
-// last-level cache rather than HBM.
 template <class R, int LB, int NT, int CM, int E>
 constexpr int lo_min_waves() {
   // two complex128 workgroups per CU (4 waves per SIMD) where the registers allow it without
@@ -232,6 +226,12 @@ constexpr int lo_min_waves() {
   return sizeof(R) == 8 && LB == 12 && NT == 512 && CM != kCoefSite ? 4 : 1;
 }
 
+// E > 0: the pass also flips the E amplitude bits LB + g0 .. LB + g0 + E - 1 (g0 =
+// p.ext_bit; the planner puts them at the top), whose neighbours lie in E other tiles of the
+// same group of 2^E tiles (those differing in tile-index bits g0 .. g0 + E - 1).  Those are
+// read straight from global memory (the input is then a stored vector): a group's tiles take
+// consecutive positions on one XCD, so most of these reads are served by its L2 or the
+// last-level cache rather than HBM.
 template <class R, int LB, int NT, int CM, int E>
 __global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_lo_kernel(const StepCoef c, const PassArgs<R> p) {
   using C = Cx<R>;

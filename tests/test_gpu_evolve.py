@@ -331,6 +331,23 @@ def test_n28_triangular_c64_against_c128(ctx):
     assert np.abs(occ_a - occ_b).max() <= 1e-5
 
 
+def test_n29_c64_against_c128(ctx):
+    """29 atoms: complex64 (13-bit low tiles extended over the 7 top bits, one high pass)
+    against complex128 (three passes, no extension), 2 quench steps with kmax 16."""
+    import torch
+    torch.cuda.empty_cache()
+    w = wl.triangular30(n_atoms=29, precision="c128")
+    a, occ_a, _, r1 = gpu_run(ctx, w, "c128", first=0, steps=2, kmax=16)
+    rsv.rsv_result_destroy(r1)
+    torch.cuda.empty_cache()
+    b, occ_b, _, r2 = gpu_run(ctx, w, "c64", first=0, steps=2, tol=1e-7, kmax=16)
+    rsv.rsv_result_destroy(r2)
+    assert observables.fidelity_loss(a, b) <= 1e-6
+    assert np.abs(occ_a - occ_b).max() <= 1e-5
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def test_n30_c64_capacity_and_time_reversal(ctx):
     """N = 30 in complex64 on one GPU (8 GiB per vector): 3 quench steps forward, then the
     reversed samples with Omega, delta and C negated bring the state back to |0...0>."""

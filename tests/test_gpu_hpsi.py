@@ -68,7 +68,8 @@ def test_interaction_diagonal(ctx, n, prec):
 
 
 CASES = [(n, ps, ph) for n in [1, 3, 7, 8, 9, 11, 12, 13, 14, 16, 21, 22, 23]
-         for ps, ph in [(False, False), (True, True)]] + [(24, True, True), (18, False, True)]
+         for ps, ph in [(False, False), (True, True)]] + [(24, True, True), (18, False, True),
+                                                          (22, False, True)]
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
