@@ -12,9 +12,10 @@
 //    two small FP64 tables (a 2^L table of the low-bit pairs, read from L2, and per tile the
 //    high-bit pairs and the low-high couplings), so no 2^n diagonal is read from HBM, plus
 //    the detuning from the bit pattern; and it adds the high-pass result t.  Where that
-//    saves a high pass, it also flips up to 7 bits above its tile, reading those neighbours
-//    from the adjacent tiles in global memory (mostly cache hits): n = 22..28 complex128
-//    and 22..29 complex64 then need one high pass (complex64 on 12-bit tiles up to n = 28).
+//    saves a high pass, it also flips up to 7 of the top bits, reading those neighbours from
+//    the other tiles of a group in global memory (mostly cache hits): n = 22..28 complex128
+//    and 22..29 complex64 then need one high pass, over the bits between (complex64 on
+//    12-bit tiles up to n = 28).
 //  * high passes (n > L): a tile of 2^r contiguous amplitudes (r = 3..6: runs of 64 B to
 //    1 KiB) times the combinations of up to H - r high bits flips those high bits.  The
 //    first high pass writes t, later ones accumulate into it.  The passes are as few as the
