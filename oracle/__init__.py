@@ -17,10 +17,23 @@ may import this package.  The HIP library never calls into it and shares no code
 the only shared module is the seeded input generator (``paper_2510_09813_amd.workloads``),
 which holds no arithmetic of the method.
 
-Parity status: every public function is pinned by ``tests/test_oracle_pins.py`` against
-closed forms (single-atom Rabi oscillation, blockaded two- and three-atom collective Rabi
-frequencies, non-interacting product states), invariants (norm, energy, time reversal,
-step splitting, mirror symmetry), brute force on tiny inputs and the published reference
-outputs of SplitMix64.  No function is "parity unpinned".
+Parity status (what pins each public function in ``tests/test_oracle_pins.py``):
+* model.interaction_matrix, interaction_energy -- hand-computed pair energies and the
+  all-excited state;
+* model.midpoint_sample, step_parameters -- the midpoint indices of Sec. III on a ramp and
+  dt^2 convergence of the midpoint scheme;
+* model.dense_hamiltonian, diagonal_tensor, apply_hamiltonian, hamiltonian_row,
+  atom_levels -- the single-atom Rabi closed form (amplitudes and phases), non-interacting
+  product states with distinct drives (bit order), the hand-derived blockade Hamiltonian
+  of two atoms and the sqrt(2), sqrt(3) collective frequencies, and agreement of the three
+  formulations;
+* evolve.evolve (dense and Lanczos), expm_lanczos -- the same closed forms, dense against
+  Lanczos, norm and energy conservation, step splitting against scipy's expm, time
+  reversal, sub-steps, the invariant subspace;
+* observables.splitmix64, uniforms -- the generator's published reference outputs;
+  occupations -- product states; sample -- brute force of its definition and a chi-square
+  test; fidelity_loss -- global phase, orthogonal and near-parallel vectors; energy --
+  basis states and the two-level expectation value written out by hand.
+Every public function has a pin; none is "parity unpinned".
 """
 from . import model, evolve, observables  # noqa: F401

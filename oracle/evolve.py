@@ -1,14 +1,15 @@
 """Time stepping of eq. (6): psi_{k+1} = exp(-i H_k dt) psi_k (Sec. III).
 
-Two independent propagators:
-* ``expm_dense``   -- exp(-i tau H) psi from numpy's Hermitian eigendecomposition of the
-                      dense H (the plain definition; small N only).
-* ``expm_lanczos`` -- the Krylov (Lanczos) approximation of Sec. III.A: build an orthonormal
-                      basis of span{psi, H psi, H^2 psi, ...} with the three-term recurrence,
-                      re-orthogonalised against every earlier vector (classical Gram-Schmidt,
-                      applied twice), then exp(-i tau T) e_1 from the eigendecomposition of the
-                      small tridiagonal T.  Converged when the a-posteriori estimate
-                      beta_m |[exp(-i tau T_m) e_1]_m| is at most tol.
+Two independent propagators, both reached through ``evolve``:
+* method "dense"   -- exp(-i tau H_k) psi from numpy's Hermitian eigendecomposition of the
+                      dense H_k (the plain definition; small N only).
+* method "lanczos" -- ``expm_lanczos``, the Krylov (Lanczos) approximation of Sec. III.A:
+                      build an orthonormal basis of span{psi, H psi, H^2 psi, ...} with the
+                      three-term recurrence, re-orthogonalised against every earlier vector
+                      (classical Gram-Schmidt, applied twice: all inner products against the
+                      same vector, w <- w - V (V^H w)), then exp(-i tau T) e_1 from the
+                      eigendecomposition of the small tridiagonal T.  Converged when the
+                      a-posteriori estimate beta_m |[exp(-i tau T_m) e_1]_m| is at most tol.
 
 Non-convergence within kmax vectors halves the step with the same H_k (exact, because
 exp(-i H tau) = exp(-i H tau/2)^2), to a depth of 8.
@@ -24,27 +25,24 @@ class NotConverged(RuntimeError):
     pass
 
 
-def expm_dense(h: np.ndarray, psi: np.ndarray, tau: float) -> np.ndarray:
-    w, v = np.linalg.eigh(h)
-    return v @ (np.exp(-1j * w * tau) * (v.conj().T @ psi))
-
-
 def expm_lanczos(apply_h, psi: np.ndarray, tau: float, tol: float, kmax: int):
     """exp(-i tau H) psi.  Returns (result, converged, krylov_dim)."""
     nrm = np.linalg.norm(psi)
     if nrm == 0.0:
         return psi.copy(), True, 0
-    basis = [psi / nrm]
+    basis = np.empty((kmax + 1, psi.size), dtype=np.complex128)  # row l = v_l
+    basis[0] = psi / nrm
     alpha, beta = [], []
     for j in range(kmax):
-        w = apply_h(basis[j])
-        a = float(np.vdot(basis[j], w).real)
-        w = w - a * basis[j]
+        v = basis[j]
+        w = apply_h(v)
+        a = float(np.vdot(v, w).real)
+        w = w - a * v
         if j > 0:
             w = w - beta[-1] * basis[j - 1]
-        for _ in range(2):
-            for v in basis:
-                w = w - np.vdot(v, w) * v
+        vs = basis[:j + 1]
+        for _ in range(2):  # classical Gram-Schmidt, twice: c_l = <v_l, w> = conj(v_l . conj(w))
+            w = w - vs.T @ np.conj(vs @ np.conj(w))
         b = float(np.linalg.norm(w))
         alpha.append(a)
         m = j + 1
@@ -53,12 +51,9 @@ def expm_lanczos(apply_h, psi: np.ndarray, tau: float, tol: float, kmax: int):
         y = q @ (np.exp(-1j * lam * tau) * q[0, :])
         err = b * abs(y[m - 1]) * nrm
         if err <= tol or b == 0.0:
-            out = np.zeros_like(psi)
-            for l in range(m):
-                out += y[l] * basis[l]
-            return nrm * out, True, m
+            return nrm * (basis[:m].T @ y), True, m
         beta.append(b)
-        basis.append(w / b)
+        basis[j + 1] = w / b
     return None, False, kmax
 
 

@@ -80,7 +80,26 @@ def dense_hamiltonian(u: np.ndarray, omega, delta, phi) -> np.ndarray:
 
 
 def diagonal_tensor(u: np.ndarray, delta) -> np.ndarray:
-    """Diagonal of H as an N-dimensional (2,...,2) tensor: sum_{i>j} U_ij n_i n_j - sum_i delta_i n_i."""
+    """Diagonal of H as an N-dimensional (2,...,2) tensor: sum_{i>j} U_ij n_i n_j - sum_i delta_i n_i.
+
+    The result depends only on (U, delta); the most recent ones are kept (see
+    ``_DIAG_CACHE``), so the many H|psi> of one time step build it once.  The cached array
+    is the one this function computes, so caching changes no arithmetic."""
+    key = (np.asarray(u, dtype=np.float64).tobytes(), np.asarray(delta, dtype=np.float64).tobytes())
+    hit = _DIAG_CACHE.get(key)
+    if hit is not None:
+        return hit
+    d = _diagonal_tensor(u, delta)
+    d.setflags(write=False)
+    _DIAG_CACHE.clear()  # one entry: at 27 atoms it is 1 GiB
+    _DIAG_CACHE[key] = d
+    return d
+
+
+_DIAG_CACHE: dict = {}
+
+
+def _diagonal_tensor(u: np.ndarray, delta) -> np.ndarray:
     n = len(delta)
     occ = [np.arange(2.0).reshape([2 if a == i else 1 for a in range(n)]) for i in range(n)]
     d = np.zeros((2,) * n)
@@ -93,20 +112,24 @@ def diagonal_tensor(u: np.ndarray, delta) -> np.ndarray:
 
 def apply_hamiltonian(psi: np.ndarray, u: np.ndarray, omega, delta, phi) -> np.ndarray:
     """H|psi> in two steps (Sec. III.A): the diagonal, then for each atom the amplitudes with
-    that atom's level swapped, scaled by the drive matrix element.  psi is handled as the
-    tensor c_{i_1...i_N}; slicing axis i at 0 or 1 selects the atom's level."""
+    that atom's level swapped, scaled by the drive matrix element.  psi is the tensor
+    c_{i_1...i_N} in row-major order, so for atom i the flat vector viewed as
+    (2^i, 2, 2^(N-1-i)) has the atom's level on its middle axis: entry [:, 0, :] holds the
+    amplitudes with atom i in |0>, entry [:, 1, :] those with atom i in |1>."""
     n = len(omega)
-    t = np.asarray(psi, dtype=np.complex128).reshape((2,) * n)
-    out = diagonal_tensor(u, delta) * t
+    x = np.asarray(psi, dtype=np.complex128).reshape(-1)
+    out = diagonal_tensor(u, delta).reshape(-1) * x
+    term = np.empty(x.size // 2, dtype=np.complex128)
     for i in range(n):
         up = 0.5 * omega[i] * np.exp(-1j * phi[i])    # <1|h_i|0>
         down = 0.5 * omega[i] * np.exp(1j * phi[i])   # <0|h_i|1>
-        lvl0 = [slice(None)] * n
-        lvl1 = [slice(None)] * n
-        lvl0[i], lvl1[i] = 0, 1
-        out[tuple(lvl1)] += up * t[tuple(lvl0)]
-        out[tuple(lvl0)] += down * t[tuple(lvl1)]
-    return out.reshape(-1)
+        shape = (1 << i, 2, 1 << (n - 1 - i))
+        t, o, tm = x.reshape(shape), out.reshape(shape), term.reshape(shape[0], shape[2])
+        np.multiply(up, t[:, 0, :], out=tm)
+        o[:, 1, :] += tm
+        np.multiply(down, t[:, 1, :], out=tm)
+        o[:, 0, :] += tm
+    return out
 
 
 def atom_levels(b: int, n: int):

@@ -305,3 +305,27 @@ def test_fidelity_loss():
     eps = 1e-7
     c = (a + eps * b / np.linalg.norm(b))
     assert observables.fidelity_loss(a, c) == pytest.approx(eps ** 2, rel=1e-6)
+
+
+def test_energy_expectation():
+    """<H> of a basis state is its diagonal entry (pair energies minus detunings); for one
+    atom in a|0> + b|1>, <H> = -delta |b|^2 + Omega Re(conj(b) a e^{-i phi})."""
+    rng = np.random.default_rng(12)
+    n = 5
+    xyz = wl.random_register(n, 12.0, 3.0, rng)
+    u = model.interaction_matrix(xyz, C6)
+    om, de, ph = rng.uniform(0, 10, n), rng.uniform(-10, 10, n), rng.uniform(-3, 3, n)
+    apply_h = lambda x: model.apply_hamiltonian(x, u, om, de, ph)
+    for b in (0, 1, 0b10110, 0b11111):
+        e = np.zeros(1 << n, dtype=complex)
+        e[b] = 1.0
+        lv = model.atom_levels(b, n)
+        want = sum(u[i, j] for i in range(n) for j in range(i) if lv[i] and lv[j]) - sum(
+            de[i] for i in range(n) if lv[i])
+        assert observables.energy(e, apply_h) == pytest.approx(want, rel=1e-14, abs=1e-12)
+    a, b = 0.6 * np.exp(0.3j), 0.8 * np.exp(-1.1j)
+    o1, d1, p1 = 3.0, 1.7, 0.9
+    want = -d1 * abs(b) ** 2 + o1 * (np.conj(b) * a * np.exp(-1j * p1)).real
+    got = observables.energy(np.array([a, b]), lambda x: model.apply_hamiltonian(
+        x, np.zeros((1, 1)), [o1], [d1], [p1]))
+    assert got == pytest.approx(want, rel=1e-14)
