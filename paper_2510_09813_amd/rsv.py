@@ -111,13 +111,66 @@ def _check(rc: int):
         raise RsvError(rc, lib().rsv_last_error().decode())
 
 
-def _dptr(buf) -> int:
-    """Device address of a torch tensor (must be contiguous) or an int address."""
-    if isinstance(buf, int):
-        return buf
+class Register:
+    """Handle of an rsv_register together with its size and precision, so that buffers
+    handed to the library can be checked before the call (ctypes passes _as_parameter_)."""
+
+    def __init__(self, handle: C.c_void_p, n_atoms: int, precision: int):
+        self._as_parameter_ = handle
+        self.n_atoms = int(n_atoms)
+        self.precision = int(precision)
+
+    @property
+    def value(self):
+        return self._as_parameter_.value
+
+
+COMPLEX_DTYPE = {RSV_C128: "complex128", RSV_C64: "complex64"}
+DTYPES = {"c128": "complex128", "c64": "complex64"}
+REAL_DTYPE = {RSV_C128: "float64", RSV_C64: "float32"}
+
+
+def _prec(precision) -> int:
+    p = PRECISIONS.get(precision, precision)
+    if p not in (RSV_C128, RSV_C64):
+        raise ValueError(f"unknown precision {precision!r}")
+    return p
+
+
+def _dptr(buf, numel: int, dtype: str, what: str) -> int:
+    """Device address of a contiguous torch tensor on a GPU holding exactly ``numel``
+    elements of ``dtype`` (the library reads and writes that many); anything else raises
+    ValueError before the library is called."""
+    import torch
+    if not isinstance(buf, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch tensor, got {type(buf).__name__}")
+    want = getattr(torch, dtype)
+    if buf.dtype != want:
+        raise ValueError(f"{what}: dtype {buf.dtype} does not match the register ({want})")
+    if buf.numel() != numel:
+        raise ValueError(f"{what}: {buf.numel()} elements, the register needs {numel}")
     if not buf.is_contiguous():
-        raise ValueError("device buffer must be contiguous")
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if not buf.is_cuda:
+        raise ValueError(f"{what}: tensor must be on a GPU, not {buf.device}")
     return int(buf.data_ptr())
+
+
+def _state_ptr(buf, n_atoms: int, precision: int, what: str) -> int:
+    return _dptr(buf, 1 << n_atoms, COMPLEX_DTYPE[precision], what)
+
+
+def _check_pulses(pulses: "PulseArrays", n_atoms: int):
+    if pulses.omega.ndim == 2 and pulses.omega.shape[0] != n_atoms:
+        raise ValueError(f"per-site pulses have {pulses.omega.shape[0]} rows, the register "
+                         f"has {n_atoms} atoms")
+
+
+def _host_state(psi0, n_atoms: int):
+    buf = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128)).reshape(-1)
+    if buf.size != 1 << n_atoms:
+        raise ValueError(f"initial state has {buf.size} amplitudes, need 2^{n_atoms}")
+    return buf
 
 
 def _stream(stream) -> Optional[int]:
@@ -144,6 +197,8 @@ class PulseArrays:
         self.phi = None if phi is None else _f64(phi)
         if self.omega.shape != self.delta.shape or (self.phi is not None and self.phi.shape != self.omega.shape):
             raise ValueError("omega, delta and phi must have the same shape")
+        if self.omega.ndim not in (1, 2) or self.omega.shape[-1] < 1:
+            raise ValueError("pulse arrays are [n_samples] or [n_atoms][n_samples]")
         pd = C.POINTER(C.c_double)
         self.struct = Pulses(self.omega.shape[-1], 1 if self.omega.ndim == 2 else 0,
                              self.omega.ctypes.data_as(pd), self.delta.ctypes.data_as(pd),
@@ -174,44 +229,51 @@ def rsv_ctx_bytes_in_use(ctx) -> int:
     return int(lib().rsv_ctx_bytes_in_use(ctx))
 
 
-def rsv_register_create(ctx, xyz, c6: float, precision="c128"):
+def rsv_register_create(ctx, xyz, c6: float, precision="c128") -> Register:
     xyz = _f64(xyz).reshape(-1, 3)
     h = C.c_void_p()
-    prec = PRECISIONS.get(precision, precision)
+    prec = _prec(precision)
     _check(lib().rsv_register_create(ctx, xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)),
                                      float(c6), prec, C.byref(h)))
-    return h
+    return Register(h, xyz.shape[0], prec)
 
 
 def rsv_register_destroy(reg):
     lib().rsv_register_destroy(reg)
 
 
-def rsv_register_diagonal(reg, d_out, stream=None):
-    _check(lib().rsv_register_diagonal(reg, _dptr(d_out), _stream(stream)))
+def rsv_register_diagonal(reg: Register, d_out, stream=None):
+    ptr = _dptr(d_out, 1 << reg.n_atoms, REAL_DTYPE[reg.precision], "diagonal")
+    _check(lib().rsv_register_diagonal(reg, ptr, _stream(stream)))
 
 
 def rsv_workspace_bytes(n_atoms: int, kmax: int, precision="c128") -> int:
     return int(lib().rsv_workspace_bytes(n_atoms, kmax, PRECISIONS.get(precision, precision)))
 
 
-def rsv_apply_hamiltonian(reg, pulses: PulseArrays, step: int, dt_ns: int, d_in, d_out, stream=None):
-    _check(lib().rsv_apply_hamiltonian(reg, C.byref(pulses.struct), step, dt_ns, _dptr(d_in),
-                                       _dptr(d_out), _stream(stream)))
+def rsv_apply_hamiltonian(reg: Register, pulses: PulseArrays, step: int, dt_ns: int, d_in, d_out,
+                          stream=None):
+    _check_pulses(pulses, reg.n_atoms)
+    pin = _state_ptr(d_in, reg.n_atoms, reg.precision, "input state")
+    pout = _state_ptr(d_out, reg.n_atoms, reg.precision, "output state")
+    _check(lib().rsv_apply_hamiltonian(reg, C.byref(pulses.struct), step, dt_ns, pin, pout,
+                                       _stream(stream)))
 
 
-def rsv_evolve_device(reg, pulses: PulseArrays, opts: EvolveOpts, d_psi, stream=None) -> Stats:
+def rsv_evolve_device(reg: Register, pulses: PulseArrays, opts: EvolveOpts, d_psi,
+                      stream=None) -> Stats:
+    _check_pulses(pulses, reg.n_atoms)
+    ptr = _state_ptr(d_psi, reg.n_atoms, reg.precision, "state")
     st = Stats()
-    _check(lib().rsv_evolve_device(reg, C.byref(pulses.struct), C.byref(opts), _dptr(d_psi),
+    _check(lib().rsv_evolve_device(reg, C.byref(pulses.struct), C.byref(opts), ptr,
                                    _stream(stream), C.byref(st)))
     return st
 
 
-def rsv_evolve(reg, pulses: PulseArrays, opts: EvolveOpts, psi0=None):
+def rsv_evolve(reg: Register, pulses: PulseArrays, opts: EvolveOpts, psi0=None):
+    _check_pulses(pulses, reg.n_atoms)
     h = C.c_void_p()
-    buf = None
-    if psi0 is not None:
-        buf = np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+    buf = None if psi0 is None else _host_state(psi0, reg.n_atoms)
     _check(lib().rsv_evolve(reg, C.byref(pulses.struct), C.byref(opts),
                             buf.ctypes.data if buf is not None else None, C.byref(h)))
     return h
@@ -245,19 +307,30 @@ def rsv_result_destroy(res):
     lib().rsv_result_destroy(res)
 
 
+def _atoms(n_atoms: int) -> int:
+    if not 1 <= int(n_atoms) <= 30:
+        raise ValueError("n_atoms must be in 1..30")
+    return int(n_atoms)
+
+
 def rsv_occupations_device(ctx, n_atoms: int, d_psi, precision="c128", stream=None) -> np.ndarray:
-    out = np.empty(n_atoms, dtype=np.float64)
-    _check(lib().rsv_occupations_device(ctx, n_atoms, PRECISIONS.get(precision, precision),
-                                        _dptr(d_psi), out.ctypes.data_as(C.POINTER(C.c_double)),
+    prec, n = _prec(precision), _atoms(n_atoms)
+    ptr = _state_ptr(d_psi, n, prec, "state")
+    out = np.empty(n, dtype=np.float64)
+    _check(lib().rsv_occupations_device(ctx, n, prec, ptr,
+                                        out.ctypes.data_as(C.POINTER(C.c_double)),
                                         _stream(stream)))
     return out
 
 
 def rsv_sample_device(ctx, n_atoms: int, d_psi, seed: int, n_shots: int, precision="c128",
                       stream=None) -> np.ndarray:
+    prec, n = _prec(precision), _atoms(n_atoms)
+    if n_shots < 0:
+        raise ValueError("n_shots must be >= 0")
+    ptr = _state_ptr(d_psi, n, prec, "state")
     out = np.empty(n_shots, dtype=np.uint64)
-    _check(lib().rsv_sample_device(ctx, n_atoms, PRECISIONS.get(precision, precision),
-                                   _dptr(d_psi), seed, n_shots,
+    _check(lib().rsv_sample_device(ctx, n, prec, ptr, seed, n_shots,
                                    out.ctypes.data_as(C.POINTER(C.c_uint64)), _stream(stream)))
     return out
 
@@ -344,7 +417,8 @@ def rsv_server_submit(srv, xyz, c6, pulses: PulseArrays, opts: EvolveOpts, preci
                       psi0=None, n_shots: int = 0, seed: int = 0, return_state: bool = False,
                       tag: int = 0) -> int:
     xyz = _f64(xyz).reshape(-1, 3)
-    buf = None if psi0 is None else np.ascontiguousarray(np.asarray(psi0, dtype=np.complex128))
+    _check_pulses(pulses, xyz.shape[0])
+    buf = None if psi0 is None else _host_state(psi0, xyz.shape[0])
     jd = JobDesc(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), float(c6),
                  PRECISIONS.get(precision, precision), pulses.struct, opts,
                  buf.ctypes.data if buf is not None else None, n_shots, seed, int(return_state), tag)
