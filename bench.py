@@ -218,7 +218,7 @@ def small_job_leg(rsv, wl, ctx, n_jobs, lanes):
 
 
 # Sources the H psi kernels are compiled from; their digest ignores comments and blank lines.
-HPSI_SOURCES = ("hpsi.hip", "common.cuh", "rsv_internal.h")
+HPSI_SOURCES = ("hpsi.hip", "device_common.h", "rsv_internal.h")
 
 
 def hpsi_code_digest(read=None):

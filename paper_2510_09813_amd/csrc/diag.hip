@@ -11,7 +11,7 @@
 // the bit-indexed U, the energy of the high bits alone and, per low bit p, the coupling
 // F_p = sum over set high bits q of U_pq; an amplitude then needs only its low-bit pairs:
 //   E_b = E_hi + sum_{p in lo(b)} (F_p + sum_{q in lo(b), q < p} U_pq).
-#include "common.cuh"
+#include "device_common.h"
 
 namespace rsv {
 namespace {

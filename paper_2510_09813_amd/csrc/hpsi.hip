@@ -33,7 +33,7 @@
 // kCoefReal (shared and phi = 0: one real coupling, the cheapest form) and kCoefSite.
 //
 // No MFMA: the operator has no dense contraction.
-#include "common.cuh"
+#include "device_common.h"
 
 namespace rsv {
 namespace {

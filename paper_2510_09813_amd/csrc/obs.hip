@@ -11,7 +11,7 @@
 // with nonzero probability.  CDF is evaluated as a prefix sum in three levels: per-block
 // sums of |psi|^2 (FP64), one exclusive scan over the blocks, then a scan inside the
 // selected block.
-#include "common.cuh"
+#include "device_common.h"
 
 namespace rsv {
 namespace {

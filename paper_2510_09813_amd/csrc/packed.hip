@@ -16,7 +16,7 @@
 //
 // Krylov vectors of a job live in global memory (L2-resident at these sizes); the newest
 // one is kept in the LDS tile, where the level swaps read it, and H u in registers.
-#include "common.cuh"
+#include "device_common.h"
 #include "packed.h"
 
 namespace rsv {

@@ -5,7 +5,7 @@
 // workgroup writes one FP64 partial in a fixed grid-stride order, then one workgroup sums
 // the partials in a fixed order (no floating-point atomics), so a result does not depend on
 // what else runs on the device.
-#include "common.cuh"
+#include "device_common.h"
 
 namespace rsv {
 namespace {
