@@ -169,6 +169,17 @@ int rsv_occupations_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const 
 int rsv_sample_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
                       uint64_t seed, int n_shots, uint64_t* idx_out, void* hip_stream);
 
+/* Allocation-free form of rsv_sample_device, for callers that cannot allocate device or
+ * pinned memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, outputs and errors; the block sums, their scan and the drawn
+ * indices live in a device array inside the library (4.7 MB on every device it runs on,
+ * kept until the process ends) instead of memory taken from the context.  n_shots at most
+ * 65536 (RSV_EINVAL beyond).  Every call on a device shares that device's array: calls that
+ * overlap in time on one device (other host threads, other streams) race and must be
+ * serialised by the caller.  idx_out is host memory; returns after the stream finished. */
+int rsv_sample_device_static(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
+                             uint64_t seed, int n_shots, uint64_t* idx_out, void* hip_stream);
+
 /* ------------------------------------------------------------------ serving
  * A server evolves a stream of independent jobs (each a register, its pulses and options)
  * on one device with continuous batching: n_lanes jobs run at once, each on its own HIP

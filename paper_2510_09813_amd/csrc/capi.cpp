@@ -91,6 +91,11 @@ int rsv_ctx_create(int hip_device, size_t budget, rsv_ctx** out) {
     delete c;
     return fail(RSV_ENOMEM, "host allocation failed");
   }
+  if (static_sample_scratch(hip_device, &c->static_scratch) != 0) {
+    delete c->dev;
+    delete c;
+    return fail(RSV_EDEVICE, "device address of the static sampling scratch not available");
+  }
   *out = c;
   return RSV_OK;
 }
@@ -261,6 +266,26 @@ int rsv_occupations_device(rsv_ctx* ctx, int n, rsv_precision prec, const void* 
 int rsv_sample_device(rsv_ctx* ctx, int n, rsv_precision prec, const void* d_psi, uint64_t seed,
                       int shots, uint64_t* out, void* stream) {
   return sample_impl(ctx, n, prec, d_psi, seed, shots, out, as_stream(stream));
+}
+
+int rsv_sample_device_static(rsv_ctx* ctx, int n, rsv_precision prec, const void* d_psi,
+                             uint64_t seed, int shots, uint64_t* out, void* stream) {
+  RSV_TRY(check_state_args(n, prec));
+  if (!ctx || !d_psi || (shots > 0 && !out)) return fail(RSV_EINVAL, "NULL argument");
+  if (shots < 0 || shots > kStaticMaxShots)
+    return fail(RSV_EINVAL, "n_shots must be in 0..%d for the allocation-free sampler",
+                kStaticMaxShots);
+  if (shots == 0) return RSV_OK;
+  if (!ctx->static_scratch) return fail(RSV_EDEVICE, "static scratch not resolved");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  // every scratch word is written before it is read (block sums, their scan, the indices)
+  double* scan = (double*)ctx->static_scratch;
+  uint64_t* d_idx = (uint64_t*)((char*)ctx->static_scratch + static_sample_idx_offset_bytes());
+  HIP_TRY(sample(prec, n, d_psi, seed, shots, scan, d_idx, s));
+  HIP_TRY(hipMemcpyAsync(out, d_idx, (size_t)shots * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return RSV_OK;
 }
 
 int rsv_tridiag_expm(int m, const double* alpha, const double* beta, double tau, double* y_re,

@@ -100,6 +100,7 @@ struct Workspace {
 struct rsv_ctx {
   int device = 0;
   rsv::DeviceAllocator* dev = nullptr;
+  void* static_scratch = nullptr;  // this device's copy of the allocation-free sampler's scratch
 };
 
 struct rsv_register {

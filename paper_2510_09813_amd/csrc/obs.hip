@@ -11,6 +11,8 @@
 // with nonzero probability.  CDF is evaluated as a prefix sum in three levels: per-block
 // sums of |psi|^2 (FP64), one exclusive scan over the blocks, then a scan inside the
 // selected block.
+#include <mutex>
+
 #include "device_common.h"
 
 namespace rsv {
@@ -218,7 +220,33 @@ __global__ __launch_bounds__(kBlock) void sample_kernel(const Cx<R>* __restrict_
   if (tid == 0) idx[blockIdx.x] = (uint64_t)base + found;
 }
 
+// Scratch of the allocation-free sampling entry point: the block sums and their exclusive
+// scan for up to kMaxAtoms atoms, then the drawn indices of up to kStaticMaxShots shots
+// (4.7 MB, held by every device the library runs on until the process ends).
+constexpr int64_t kStaticBlocks = int64_t(1) << (kMaxAtoms - kChunkBits);
+constexpr size_t kStaticIdxOffset = (size_t)(2 * kStaticBlocks + 1 + 31) / 32 * 32;  // doubles
+constexpr size_t kStaticDoubles = kStaticIdxOffset + kStaticMaxShots;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
 }  // namespace
+
+int static_sample_scratch(int device, void** out) {
+  // The array's host-side name is not a device address: its address on each device comes
+  // from the runtime, once per device, with that device current.
+  static std::mutex mu;
+  static void* addr[64] = {};
+  if (device < 0 || device >= 64) return -1;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return 0;
+}
+
+size_t static_sample_idx_offset_bytes() { return kStaticIdxOffset * sizeof(double); }
 
 int64_t occ_num_partials(int n) {
   const int cbits = n < kChunkBits ? n : kChunkBits;

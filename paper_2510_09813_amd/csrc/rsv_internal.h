@@ -141,6 +141,13 @@ int64_t sample_scratch_doubles(int n);
 // idx[s] for s < shots; scratch holds sample_scratch_doubles(n) doubles.
 hipError_t sample(int prec, int n, const void* x, uint64_t seed, int shots, double* scratch,
                   uint64_t* idx, hipStream_t s);
+// The allocation-free sampler's scratch: a file-scope device array of
+// sample_scratch_doubles(kMaxAtoms) doubles followed by room for kStaticMaxShots indices.
+// static_sample_scratch gives its address on `device` (which must be current), resolved once
+// per device; 0 on success.
+constexpr int kStaticMaxShots = 1 << 16;
+int static_sample_scratch(int device, void** out);
+size_t static_sample_idx_offset_bytes();
 
 // --------------------------------------------------------------------------- host FP64
 // Eigendecomposition of the symmetric tridiagonal T (alpha: m diagonal, beta: m-1

@@ -27,7 +27,8 @@ EXPORTED = [
     "rsv_register_create", "rsv_register_destroy", "rsv_register_diagonal", "rsv_workspace_bytes",
     "rsv_apply_hamiltonian", "rsv_evolve_device", "rsv_evolve", "rsv_result_state",
     "rsv_result_occupations", "rsv_result_sample", "rsv_result_stats", "rsv_result_destroy",
-    "rsv_occupations_device", "rsv_sample_device", "rsv_tridiag_expm",
+    "rsv_occupations_device", "rsv_sample_device", "rsv_sample_device_static",
+    "rsv_tridiag_expm",
 ]
 
 
@@ -96,6 +97,8 @@ def lib():
         "rsv_result_destroy": (None, [vp]),
         "rsv_occupations_device": (i32, [vp, i32, i32, vp, pd, vp]),
         "rsv_sample_device": (i32, [vp, i32, i32, vp, u64, i32, C.POINTER(C.c_uint64), vp]),
+        "rsv_sample_device_static": (i32, [vp, i32, i32, vp, u64, i32, C.POINTER(C.c_uint64),
+                                           vp]),
         "rsv_tridiag_expm": (i32, [i32, pd, pd, dbl, pd, pd]),
     }
     for name, (res, args) in sig.items():
@@ -332,6 +335,19 @@ def rsv_sample_device(ctx, n_atoms: int, d_psi, seed: int, n_shots: int, precisi
     out = np.empty(n_shots, dtype=np.uint64)
     _check(lib().rsv_sample_device(ctx, n, prec, ptr, seed, n_shots,
                                    out.ctypes.data_as(C.POINTER(C.c_uint64)), _stream(stream)))
+    return out
+
+
+def rsv_sample_device_static(ctx, n_atoms: int, d_psi, seed: int, n_shots: int,
+                             precision="c128", stream=None) -> np.ndarray:
+    prec, n = _prec(precision), _atoms(n_atoms)
+    if n_shots < 0:
+        raise ValueError("n_shots must be >= 0")
+    ptr = _state_ptr(d_psi, n, prec, "state")
+    out = np.empty(n_shots, dtype=np.uint64)
+    _check(lib().rsv_sample_device_static(ctx, n, prec, ptr, seed, n_shots,
+                                          out.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                          _stream(stream)))
     return out
 
 
