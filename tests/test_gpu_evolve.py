@@ -4,17 +4,20 @@ CPU oracle, its outputs (<n_i>, samples), invariants at full size and error hand
 Bars (from the method, not tuned): state infidelity 1 - |<psi_ref|psi>|^2 <= 1e-10 in
 complex128 and <= 1e-6 in complex64; occupations within 1e-8 (c128) / 1e-5 (c64).
 """
+import os
+
 import numpy as np
 import pytest
 
 from oracle import evolve, model, observables
 from paper_2510_09813_amd import rsv
 from paper_2510_09813_amd import workloads as wl
-from tests.gpu_util import to_dev, to_host
+from tests.gpu_util import assert_valid_samples, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 INFID = {"c128": 1e-10, "c64": 1e-6}
 OCC = {"c128": 1e-8, "c64": 1e-5}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -61,9 +64,11 @@ def test_chain10_full_run(ctx, prec):
         check(psi, occ, ref, prec)
         assert st["steps"] == 100 and st["krylov_iters"] >= 100
         shots = rsv.rsv_result_sample(res, w.seed, w.n_shots)
-        want = observables.sample(ref if prec == "c128" else psi, w.seed, w.n_shots)
-        same = np.count_nonzero(shots == want)
-        assert same >= 999, same
+        # the sampler on its own input: every shot correct, at most one at a rounding boundary
+        assert_valid_samples(shots, psi, w.seed, 999)
+        if prec == "c128":  # end to end: shot by shot against the oracle's final state
+            same = np.count_nonzero(shots == observables.sample(ref, w.seed, w.n_shots))
+            assert same >= 999, same
         assert np.all(shots < (1 << 10))
         np.testing.assert_allclose(occ, occ[::-1], atol=OCC[prec])  # mirror symmetry
     finally:
@@ -111,6 +116,24 @@ def test_square20_window(ctx):
     check(psi, occ, ref, "c128")
 
 
+@pytest.fixture(scope="module")
+def n22_window():
+    """The first register size whose low pass flips bits held in neighbouring tiles (22
+    atoms, two bits): 2 plateau steps of the random-register sweep from |0...0> by the
+    Krylov oracle (about a minute on the host)."""
+    w = wl.random27(n_atoms=22)
+    return w, evolve.evolve_workload(w, steps=2, first_step=200, tol=1e-13)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_n22_window_against_lanczos_oracle(ctx, n22_window, prec):
+    w, ref = n22_window
+    psi, occ, st, res = gpu_run(ctx, w, prec, first=200, steps=2)
+    rsv.rsv_result_destroy(res)
+    assert st["steps"] == 2
+    check(psi, occ, ref, prec)
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_n27_time_reversal(ctx, prec):
     """27 atoms, full size: 8 forward steps of the sweep, then the reversed samples with
@@ -133,15 +156,21 @@ def test_n27_time_reversal(ctx, prec):
 
 
 def test_n27_c64_against_c128(ctx):
-    """Mixed precision on the 27-atom register: complex64 state, FP64 Lanczos scalars."""
+    """Mixed precision on the 27-atom register over the whole sweep (400 steps from
+    |0...0>): complex64 state and Krylov basis with FP64 Lanczos scalars (tol 1e-7) against
+    the complex128 run (tol 1e-10); the infidelity and the largest occupation error are
+    printed."""
     w = wl.random27()
-    psi0 = None
-    a, occ_a, _, r1 = gpu_run(ctx, w, "c128", psi0=psi0, first=150, steps=10)
-    b, occ_b, _, r2 = gpu_run(ctx, w, "c64", psi0=psi0, first=150, steps=10)
+    a, occ_a, st_a, r1 = gpu_run(ctx, w, "c128")
     rsv.rsv_result_destroy(r1)
+    b, occ_b, st_b, r2 = gpu_run(ctx, w, "c64")
     rsv.rsv_result_destroy(r2)
-    assert observables.fidelity_loss(a, b) <= 1e-6
-    assert np.abs(occ_a - occ_b).max() <= 1e-5
+    assert st_a["steps"] == st_b["steps"] == w.n_steps
+    loss, docc = observables.fidelity_loss(a, b), float(np.abs(occ_a - occ_b).max())
+    print(f"random27 c64 vs c128 after {w.n_steps} steps: infidelity {loss:.3e}, "
+          f"max |d<n_i>| {docc:.3e}")
+    assert loss <= 1e-6
+    assert docc <= 1e-5
 
 
 @pytest.mark.parametrize("prec,n", [("c128", 24), ("c128", 26), ("c64", 25)])
@@ -307,9 +336,7 @@ def test_observables_of_device_states(ctx, n, prec):
     occ = rsv.rsv_occupations_device(ctx, n, d, prec)
     np.testing.assert_allclose(occ, observables.occupations(psi), atol=1e-12)
     shots = rsv.rsv_sample_device(ctx, n, d, 7, 4000, prec)
-    want = observables.sample(psi, 7, 4000)
-    agree = np.count_nonzero(shots == want)
-    assert agree >= 3996, agree
+    assert_valid_samples(shots, psi, 7, 3996)
     p = observables.probabilities(psi)
     assert np.all(p[shots.astype(np.int64)] > 0)
     # the empirical mean of each atom's level stays within 5 sigma of <n_i>

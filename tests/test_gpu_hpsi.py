@@ -95,14 +95,37 @@ def test_hpsi_matches_oracle(ctx, n, per_site, phase, prec):
 
 SAMPLED = [("c128", 27, False), ("c128", 27, True), ("c64", 27, False), ("c64", 27, True),
            ("c128", 25, True), ("c128", 26, False), ("c128", 28, True), ("c64", 26, True),
-           ("c64", 28, False), ("c64", 29, True)]
+           ("c64", 28, False), ("c64", 29, True), ("c128", 29, True), ("c64", 30, False)]
+
+
+class Gathered:
+    """Amplitudes of a device vector at a set of indices, as complex128, indexable like the
+    full vector (only those indices): the rows below need each sampled index and its N
+    neighbours, not the whole 2^N vector on the host."""
+
+    def __init__(self, d_vec, indices):
+        import torch
+        self.keys = np.unique(np.asarray(indices, dtype=np.int64))
+        sel = torch.from_numpy(self.keys).to(d_vec.device)
+        self.vals = d_vec[sel].cpu().numpy().astype(np.complex128)
+        self.pos = {int(k): i for i, k in enumerate(self.keys)}
+
+    def __getitem__(self, b):
+        return self.vals[self.pos[int(b)]]
+
+    def abs(self):
+        g = object.__new__(Gathered)
+        g.keys, g.pos, g.vals = self.keys, self.pos, np.abs(self.vals)
+        return g
 
 
 @pytest.mark.parametrize("prec,n,per_site", SAMPLED)
 def test_hpsi_full_size_sampled(ctx, prec, n, per_site):
     """The random register at full sizes (27 atoms: the launch configuration the benchmark
     times; 25..29: low passes that flip 4..7 bits of neighbouring tiles, on 12- and 13-bit
-    tiles): 2000 sampled rows computed one by one from the matrix elements."""
+    tiles; complex128 at 29 and complex64 at 30 atoms: the plans whose second high pass
+    accumulates into the first one's partial): 2000 sampled rows computed one by one from
+    the matrix elements."""
     w = wl.random27(n_atoms=n, precision=prec)
     n = w.n_atoms
     rng = np.random.default_rng(42)
@@ -125,11 +148,13 @@ def test_hpsi_full_size_sampled(ctx, prec, n, per_site):
                           rng.integers(0, 1 << n, 1994)])
     u = model.interaction_matrix(w.xyz, w.c6)
     pars = model.step_parameters(n, om, de, ph, w.dt_ns, step)
-    psi_h = d_in.cpu().numpy().astype(np.complex128)
-    got = d_out.cpu().numpy().astype(np.complex128)[idx]
+    nbrs = np.concatenate([idx] + [idx ^ (1 << p) for p in range(n)])
+    psi_h = Gathered(d_in, nbrs)
+    got = Gathered(d_out, idx)
+    got = np.array([got[b] for b in idx])
     ref = np.array([model.hamiltonian_row(int(b), psi_h, u, *pars) for b in idx])
     # per-row bound: the sum of the magnitudes of the row's terms
-    abs_psi, abs_u = np.abs(psi_h), np.abs(u)
+    abs_psi, abs_u = psi_h.abs(), np.abs(u)
     om_abs, de_neg = np.abs(pars[0]), -np.abs(pars[1])
     bound = np.array([model.hamiltonian_row(int(b), abs_psi, abs_u, om_abs, de_neg,
                                             np.zeros(n)).real for b in idx])

@@ -8,6 +8,7 @@ import pytest
 from oracle import evolve, observables
 from paper_2510_09813_amd import rsv
 from paper_2510_09813_amd import workloads as wl
+from tests.gpu_util import assert_valid_samples
 
 pytestmark = pytest.mark.gpu
 
@@ -153,7 +154,7 @@ def test_rejections_and_cancel(ctx):
 
 # ---------------------------------------------------------------------- packed small jobs
 PACK = {"c128": 12, "c64": 13}
-FID = {"c128": 1e-9, "c64": 2e-5}
+FID = {"c128": 1e-10, "c64": 1e-6}
 
 
 def packed_cases(prec):
@@ -219,8 +220,7 @@ def test_packed_matches_oracle_and_plain_path(ctx, prec):
         # outputs of the packed path are those of its own final state
         np.testing.assert_allclose(c["occupations"], observables.occupations(c["state"]),
                                    atol=1e-12)
-        want = observables.sample(c["state"], 17, 500)
-        assert np.count_nonzero(c["samples"] == want) >= 498
+        assert_valid_samples(c["samples"], c["state"], 17, 498)
         st = c["stats"]
         assert st["steps"] == w.n_steps and st["krylov_iters"] >= w.n_steps
         assert 1 <= st["krylov_max"] <= w.kmax
@@ -267,7 +267,7 @@ def test_packed_strong_interactions_and_errors(ctx):
         assert done[t]["status"] == rsv.RSV_OK, done[t]["error"]
         assert done[t]["stats"]["substeps"] > 0
         ref = evolve.evolve_workload(w, method="dense")
-        assert observables.fidelity_loss(ref, done[t]["state"]) <= 1e-9
+        assert observables.fidelity_loss(ref, done[t]["state"]) <= 1e-10
     assert np.array_equal(done[0]["state"], done[2]["state"])
 
 
