@@ -15,7 +15,12 @@ first (steps 0..W-1 from |0...0>), then K steps are timed (steps W..W+K-1).  Rep
              compulsory traffic is 32 B/amplitude (reported beside it),
   c64        the same for complex64 storage with FP64 Lanczos scalars, plus its infidelity
              against the complex128 result of the same steps,
-  cpu_baseline  the CPU oracle's H psi at the same size, scaled to sim-us/s.
+  n30_c64    the 30-atom triangular quench in complex64: ms per step and workspace,
+  serving    the mixed-size stream: saturation solves/s, steady-state p50/p99 at 0.8 x
+             saturation, the sequential complex128 plain path's rate and latencies, and the
+             infidelity and occupation error of every served result against complex128,
+  cpu_baseline  one time step of the CPU oracle, scaled to sim-us/s at 27 atoms.
+Every leg logs its progress to stderr at least every 20 s.
 """
 from __future__ import annotations
 
@@ -90,90 +95,160 @@ def evolve_timed(rsv, ctx, w, prec, warmup, steps):
     psi = torch.zeros(1 << w.n_atoms, dtype=dt, device="cuda:0")
     psi[0] = 1
     tol = w.tol if prec == "c128" else 1e-7
-    st_w = rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, tol, w.kmax, 12, 0, warmup), psi)
-    log(f"{prec}: warmup {warmup} steps in {st_w.seconds:.2f} s")
+
+    def run(first, count, what):
+        # calls of at most 50 steps (stepping is Markov: (k, psi_k) resumes exactly), each
+        # followed by a progress line
+        iters, kmax = 0, 0
+        for f in range(first, first + count, 50):
+            c = min(50, first + count - f)
+            st = rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, tol, w.kmax, 12, f, c), psi)
+            iters += st.krylov_iters
+            kmax = max(kmax, st.krylov_max)
+            log(f"{prec} {what}: steps {f}..{f + c - 1} done")
+        return iters, kmax
+
+    run(0, warmup, "warmup")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, tol, w.kmax, 12, warmup, steps), psi)
+    iters, kmax = run(warmup, steps, "timed")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log(f"{prec}: {steps} steps in {wall:.3f} s, {st.krylov_iters} Krylov iterations")
-    return reg, psi, st, wall
+    log(f"{prec}: {steps} steps in {wall:.3f} s, {iters} Krylov iterations")
+    return reg, psi, {"krylov_iters": iters, "krylov_max": kmax}, wall
 
 
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def serving_leg(rsv, wl, ctx, n_jobs, lanes):
-    """Mixed-size serving stream (N ~ U{12..24}, random registers and piecewise-linear
-    pulses, complex64 with FP64 reductions, tol 1e-7): the sequential complex128 plain path
-    gives the service times mu_seq and the FP64 reference states; the server then takes the
-    same jobs at Poisson arrivals of rate 2 mu_seq.  Sequential latencies replay the same
-    arrival trace against the measured sequential service times."""
-    jobs = wl.serving_stream(n_jobs, seed=0)
-    ref, service = [], []
-    for w in jobs:
-        reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c128")
-        t0 = time.perf_counter()
-        res = rsv.rsv_evolve(reg, rsv.PulseArrays(w.omega, w.delta),
-                             rsv.evolve_opts(w.dt_ns, 1e-10, w.kmax, 12))
-        rsv.rsv_result_occupations(res, w.n_atoms)
-        service.append(time.perf_counter() - t0)
-        ref.append(rsv.rsv_result_state(res, w.n_atoms))
-        rsv.rsv_result_destroy(res)
-        rsv.rsv_register_destroy(reg)
-    mu_seq = len(jobs) / sum(service)
-    log(f"serving: sequential complex128 plain path {mu_seq:.2f} solves/s over {len(jobs)} jobs")
-    rate = 2.0 * mu_seq
-    arrivals = wl.poisson_arrivals(len(jobs), rate, seed=1)
-    seq_lat, t_free = [], 0.0
-    for a, s in zip(arrivals, service):
-        t_free = max(t_free, a) + s
-        seq_lat.append(t_free - a)
+class Progress:
+    """A line on stderr at most every `every` seconds from inside long loops."""
 
-    arena = 2 * sum(sorted(rsv.rsv_server_job_bytes(w.n_atoms, w.kmax, "c64", 0) for w in jobs)[-lanes:])
+    def __init__(self, what, every=20.0):
+        self.what, self.every, self.t = what, every, time.perf_counter()
+
+    def __call__(self, msg):
+        now = time.perf_counter()
+        if now - self.t >= self.every:
+            log(f"{self.what}: {msg}")
+            self.t = now
+
+
+def infidelity(a, b):
+    a = a / np.linalg.norm(a)
+    b = b / np.linalg.norm(b)
+    r = b - np.vdot(a, b) * a
+    return float(np.vdot(r, r).real)
+
+
+def occupations_of(psi):
+    """<n_i> of a host state (atom 0 = most significant bit): only used to report the
+    occupation error of served results against the complex128 results."""
+    p = np.abs(psi) ** 2
+    n = int(round(np.log2(p.size)))
+    t = p.reshape((2,) * n)
+    return np.array([np.take(t, 1, axis=i).sum() for i in range(n)]) / p.sum()
+
+
+def serve_jobs(rsv, ctx, jobs, lanes, arena, arrivals=None):
+    """Runs jobs through one server (complex64, jobs of <= 13 atoms packed); arrivals[i] is
+    job i's submission time in seconds from the start (None: all at once).  Returns the
+    completions and the wall span from the first submission to the last completion."""
     srv = rsv.rsv_server_create(ctx, n_lanes=lanes, arena_bytes=arena, pack_max_atoms=13)
-    done = []
+    done, prog = [], Progress("serving")
     try:
         pulses = [rsv.PulseArrays(w.omega, w.delta) for w in jobs]
         t_start = time.perf_counter()
         for i, w in enumerate(jobs):
-            while time.perf_counter() - t_start < arrivals[i]:
-                done += rsv.rsv_server_poll(srv, 64, 1)
-            rsv.rsv_server_submit(srv, w.xyz, w.c6, pulses[i], rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12),
-                                  "c64", return_state=True, tag=i)
+            if arrivals is not None:
+                while time.perf_counter() - t_start < arrivals[i]:
+                    done += rsv.rsv_server_poll(srv, 64, 1)
+                    prog(f"{len(done)} of {len(jobs)} done, {i} submitted")
+            rsv.rsv_server_submit(srv, w.xyz, w.c6, pulses[i],
+                                  rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12), "c64",
+                                  return_state=True, tag=i)
         while len(done) < len(jobs):
             done += rsv.rsv_server_poll(srv, 64, 1000)
+            prog(f"{len(done)} of {len(jobs)} done")
     finally:
         rsv.rsv_server_destroy(srv)
     bad = [c for c in done if c["status"] != 0]
     assert not bad, bad[0]["error"]
-    lat = [c["t_end"] - c["t_submit"] for c in done]
     span = max(c["t_end"] for c in done) - min(c["t_submit"] for c in done)
-    infid = []
-    for c in done:
-        a, b = ref[c["tag"]], c["state"]
-        a = a / np.linalg.norm(a)
-        b = b / np.linalg.norm(b)
-        r = b - np.vdot(a, b) * a
-        infid.append(float(np.vdot(r, r).real))
-    seq_span = t_free - arrivals[0]
+    return sorted(done, key=lambda c: c["tag"]), span
+
+
+def serving_leg(rsv, wl, ctx, n_jobs, lanes):
+    """Mixed-size serving stream: the first n_jobs jobs of the 2000-job recipe (N ~
+    U{12..24}, random registers and piecewise-linear pulses, complex64 with FP64
+    reductions, tol 1e-7; job i's inputs do not depend on n_jobs).
+      1. the sequential complex128 plain path, job after job: its service rate and the FP64
+         reference state and occupations of every job;
+      2. saturation: every job submitted at t = 0 to the server, served solves/s;
+      3. steady state: Poisson arrivals at 0.8 x the saturation throughput, served p50/p99
+         latency, and the sequential path's latency on the same arrival trace (replayed
+         against its measured service times).
+    Every served result of runs 2 and 3 is compared with its complex128 result."""
+    jobs = wl.serving_stream(n_jobs, seed=0)
+    ref, ref_occ, service = [], [], []
+    prog = Progress("serving reference")
+    for i, w in enumerate(jobs):
+        reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c128")
+        t0 = time.perf_counter()
+        res = rsv.rsv_evolve(reg, rsv.PulseArrays(w.omega, w.delta),
+                             rsv.evolve_opts(w.dt_ns, 1e-10, w.kmax, 12))
+        ref_occ.append(rsv.rsv_result_occupations(res, w.n_atoms))
+        service.append(time.perf_counter() - t0)
+        ref.append(rsv.rsv_result_state(res, w.n_atoms))
+        rsv.rsv_result_destroy(res)
+        rsv.rsv_register_destroy(reg)
+        prog(f"{i + 1} of {len(jobs)} jobs")
+    mu_seq = len(jobs) / sum(service)
+    log(f"serving: sequential complex128 plain path {mu_seq:.2f} solves/s over {len(jobs)} jobs")
+
+    arena = 2 * sum(sorted(rsv.rsv_server_job_bytes(w.n_atoms, w.kmax, "c64", 0) for w in jobs)[-lanes:])
+    sat, sat_span = serve_jobs(rsv, ctx, jobs, lanes, arena)
+    capacity = len(jobs) / sat_span
+    log(f"serving: saturation {capacity:.3f} solves/s (all {len(jobs)} jobs at t = 0)")
+    rate = 0.8 * capacity
+    arrivals = wl.poisson_arrivals(len(jobs), rate, seed=1)
+    arrivals = arrivals - arrivals[0]
+    steady, span = serve_jobs(rsv, ctx, jobs, lanes, arena, arrivals)
+    lat = [c["t_end"] - c["t_submit"] for c in steady]
+    seq_lat, t_free = [], 0.0
+    for a, s_ in zip(arrivals, service):
+        t_free = max(t_free, a) + s_
+        seq_lat.append(t_free - a)
+
+    def errors(done):
+        inf = [infidelity(ref[c["tag"]], c["state"]) for c in done]
+        docc = [float(np.abs(c["occupations"] - ref_occ[c["tag"]]).max()) for c in done]
+        return inf, docc
+
+    inf_sat, docc_sat = errors(sat)
+    inf_st, docc_st = errors(steady)
     out = {
-        "jobs": len(jobs), "lanes": lanes, "arrival_rate_per_s": round(rate, 3),
+        "config": {"jobs": len(jobs), "of_stream": 2000, "n_atoms": "12..24", "lanes": lanes,
+                   "precision": "c64 state, FP64 reductions, tol 1e-7; jobs <= 13 atoms packed",
+                   "reference": "sequential complex128 plain path, tol 1e-10"},
         "n_atoms": [int(w.n_atoms) for w in jobs],
+        "saturation_solves_per_s": round(capacity, 3),
+        "arrival_rate_per_s": round(rate, 3),
         "served_solves_per_s": round(len(jobs) / span, 3),
         "served_p50_s": round(percentile(lat, 50), 4), "served_p99_s": round(percentile(lat, 99), 4),
-        "sequential_c128_solves_per_s": round(len(jobs) / seq_span, 3),
         "sequential_c128_service_solves_per_s": round(mu_seq, 3),
         "sequential_p50_s": round(percentile(seq_lat, 50), 4),
         "sequential_p99_s": round(percentile(seq_lat, 99), 4),
-        "max_infidelity_vs_c128": max(infid),
+        "max_infidelity_vs_c128": max(inf_sat + inf_st),
+        "max_occ_err_vs_c128": max(docc_sat + docc_st),
+        "per_job_infidelity": [float(f"{x:.3g}") for x in inf_sat],
+        "per_job_max_occ_err": [float(f"{x:.3g}") for x in docc_sat],
         "packed_jobs": sum(1 for w in jobs if w.n_atoms <= 13),
-        "precision": "c64 state, FP64 reductions, tol 1e-7",
     }
-    log(f"serving: {out['served_solves_per_s']} solves/s, p50 {out['served_p50_s']} s, "
-        f"p99 {out['served_p99_s']} s; max infidelity {out['max_infidelity_vs_c128']:.2e}")
+    log(f"serving: steady state at {rate:.3f}/s: {out['served_solves_per_s']} solves/s, p50 "
+        f"{out['served_p50_s']} s, p99 {out['served_p99_s']} s; max infidelity "
+        f"{out['max_infidelity_vs_c128']:.2e}")
     return out
 
 
@@ -192,22 +267,17 @@ def small_job_leg(rsv, wl, ctx, n_jobs, lanes):
                 rsv.rsv_server_submit(srv, w.xyz, w.c6, rsv.PulseArrays(w.omega, w.delta),
                                       rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12), "c64",
                                       return_state=True, tag=i)
-            done = []
+            done, prog = [], Progress(f"small jobs ({mode})")
             while len(done) < len(jobs):
                 done += rsv.rsv_server_poll(srv, 256, 1000)
+                prog(f"{len(done)} of {len(jobs)} done")
             span = time.perf_counter() - t0
         finally:
             rsv.rsv_server_destroy(srv)
         bad = [c for c in done if c["status"] != 0]
         assert not bad, bad[0]["error"]
         res[mode] = ({c["tag"]: c["state"] for c in done}, span)
-    infid = []
-    for i in range(len(jobs)):
-        a, b = res["plain"][0][i], res["packed"][0][i]
-        a = a / np.linalg.norm(a)
-        b = b / np.linalg.norm(b)
-        r = b - np.vdot(a, b) * a
-        infid.append(float(np.vdot(r, r).real))
+    infid = [infidelity(res["plain"][0][i], res["packed"][0][i]) for i in range(len(jobs))]
     out = {"jobs": len(jobs), "n_atoms": "6..13", "lanes": lanes,
            "plain_solves_per_s": round(len(jobs) / res["plain"][1], 2),
            "packed_solves_per_s": round(len(jobs) / res["packed"][1], 2),
@@ -248,49 +318,95 @@ def pmc_traffic(prec):
     return rec.get("bytes_per_application")
 
 
-def cpu_baseline(w, iters_per_step, budget_s=20.0):
-    """The oracle on the host: rows (H psi)_b of the N = 27 H|psi> at the step-300
-    parameters, evaluated one by one from the matrix elements (the oracle's form that works
-    at this size), timed for about budget_s; the time per row scales to one H|psi>
-    (2^27 rows) and, with the GPU run's H|psi> count per step, to simulated us per second.
-    The oracle's Lanczos re-orthogonalisation and combination are not counted."""
-    from oracle import model
-    n = w.n_atoms
-    rng = np.random.default_rng(42)
-    psi = (rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)).astype(np.complex128)
-    u = model.interaction_matrix(w.xyz, w.c6)
-    pars = model.step_parameters(n, w.omega, w.delta, None, w.dt_ns, 300)
-    rows = rng.integers(0, 1 << n, 200000)
+def capacity_leg(rsv, wl, ctx, steps):
+    """The 5x6 triangular quench at 30 atoms in complex64 (FP64 Lanczos scalars and host
+    tridiagonal exponential, kmax 20, dt = 5 ns): the first `steps` steps from |0...0>."""
+    import torch
+    w = wl.triangular30()
+    ws = rsv.rsv_workspace_bytes(w.n_atoms, w.kmax, "c64")
+    reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c64")
+    psi = torch.zeros(1 << w.n_atoms, dtype=torch.complex64, device="cuda:0")
+    psi[0] = 1
+    pulses = rsv.PulseArrays(w.omega, w.delta)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
-    while done < rows.size and time.perf_counter() - t0 < budget_s:
-        for b in rows[done:done + 500]:
-            model.hamiltonian_row(int(b), psi, u, *pars)
-        done += 500
-    t_row = (time.perf_counter() - t0) / done
-    t_apply = t_row * (1 << n)
-    step_s = t_apply * iters_per_step
+    st = rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12, 0, steps), psi)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    occ = rsv.rsv_occupations_device(ctx, w.n_atoms, psi, "c64")
+    out = {"workload": "triangular30-quench", "n_atoms": w.n_atoms, "precision": "complex64",
+           "steps": steps, "ms_per_step": round(wall / steps * 1e3, 2),
+           "sim_us_per_s": round(steps * w.dt_ns * 1e-3 / wall, 5),
+           "krylov_iters_per_step": round(st.krylov_iters / steps, 2),
+           "krylov_max": int(st.krylov_max), "norm_final": st.norm_final,
+           "workspace_bytes": int(ws), "workspace_gib": round(ws / 2**30, 2),
+           "device_bytes_in_use": int(rsv.rsv_ctx_bytes_in_use(ctx)),
+           "occupations_sum": round(float(occ.sum()), 6)}
+    log(f"N=30 c64: {steps} steps in {wall:.2f} s, workspace {ws / 2**30:.1f} GiB")
+    rsv.rsv_register_destroy(reg)
+    del psi
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(wl, gpu_iters_per_step):
+    """The CPU oracle as it stands, on the host: one complete time step of its Krylov
+    propagator (diagonal tensor, Lanczos with full re-orthogonalisation, tol 1e-13,
+    combination) on the random-register sweep recipe at 20 atoms (plateau step 300, from a
+    random normalised state), timed on one BLAS thread and on every core; the all-core time
+    is scaled to 27 atoms by 2^7 x 27/20 (its per-iteration work is O(N 2^N) for H psi and
+    O(m 2^N) for the re-orthogonalisation) and reported as simulated us per second.  The
+    complete 10-atom chain run (dense eigendecomposition, 100 steps) is timed as well."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import evolve
+    n = 20
+    w = wl.random27(n_atoms=n)
+    psi0 = wl.random_state(n, np.random.default_rng(42))
+    cores = len(os.sched_getaffinity(0))
+    blas = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    times = {}
+    for label, limit in (("all_cores", None), ("one_thread", 1)):
+        with threadpool_limits(limits=limit):
+            t0 = time.perf_counter()
+            _, st = evolve.evolve_workload(w, psi0=psi0, steps=1, first_step=300, tol=1e-13,
+                                           return_stats=True)
+            times[label] = time.perf_counter() - t0
+        log(f"cpu baseline: oracle step at N={n} ({label}) {times[label]:.1f} s, "
+            f"{st['iters']} Krylov iterations")
+    c1 = wl.chain10()
+    t0 = time.perf_counter()
+    evolve.evolve_workload(c1, method="dense")
+    t_chain = time.perf_counter() - t0
+    scale = 2.0 ** (27 - n) * 27.0 / n
+    step27 = times["all_cores"] * scale
     return {
-        "value": w.dt_ns * 1e-3 / step_s, "unit": "sim-us/s", "cores": 1, "kind": "oracle",
-        "sample": (f"{done} rows of the N={n} H|psi> (random rows, step-300 parameters) from the "
-                   f"oracle's per-row form, {t_row * 1e6:.1f} us per row on 1 host thread; "
-                   f"scaled to 2^{n} rows per H|psi> and the GPU run's {iters_per_step:.2f} "
-                   f"H|psi> per step; re-orthogonalisation and combination not counted"),
-        "hpsi_seconds_extrapolated": t_apply,
-        "host_cpus": len(os.sched_getaffinity(0)),
+        "value": w.dt_ns * 1e-3 / step27, "unit": "sim-us/s", "cores": cores, "kind": "oracle",
+        "sample": (f"one oracle time step (Krylov propagator with full re-orthogonalisation, "
+                   f"tol 1e-13; {st['iters']} iterations) of the random-register sweep at "
+                   f"N={n}, plateau step 300, random state: {times['all_cores']:.2f} s on "
+                   f"{cores} cores (BLAS {blas} threads), {times['one_thread']:.2f} s on one "
+                   f"thread; scaled to N=27 by 2^7 x 27/20 = {scale:.0f}"),
+        "oracle_step_s_n20_all_cores": round(times["all_cores"], 3),
+        "oracle_step_s_n20_one_thread": round(times["one_thread"], 3),
+        "oracle_iters_n20": int(st["iters"]), "gpu_iters_per_step_n27": gpu_iters_per_step,
+        "blas_threads": blas, "host_cpus": cores,
+        "chain10_full_run_s": round(t_chain, 3),
     }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=40,
+    ap.add_argument("--serve-jobs", type=int, default=100,
                     help="jobs of the mixed-size serving stream (0: skip the serving leg)")
     ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--n30-steps", type=int, default=3,
+                    help="steps of the 30-atom complex64 leg (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state vector of one job lives on one MI355X; "
@@ -313,7 +429,7 @@ def main():
     log(f"device copy of 2 GiB: {cp_ms:.3f} ms = {cp_gbs:.0f} GB/s (read + write)")
     reg128, psi128, st128, wall128 = evolve_timed(rsv, ctx, w, "c128", W, K)
     sim_us = K * w.dt_ns * 1e-3
-    iters_per_step = st128.krylov_iters / K
+    iters_per_step = st128['krylov_iters'] / K
 
     pulses = rsv.PulseArrays(w.omega, w.delta)
     ms128 = hpsi_time(rsv, reg128, pulses, 300, w.dt_ns, n, "c128")
@@ -330,7 +446,7 @@ def main():
                    "dt_ns": w.dt_ns, "tol": w.tol, "kmax": w.kmax,
                    "timed_steps": f"{W}..{W + K - 1} of {w.n_steps}", "precision": "complex128"},
         "krylov_iters_per_step": round(iters_per_step, 3),
-        "krylov_max": int(st128.krylov_max),
+        "krylov_max": int(st128['krylov_max']),
         "hpsi_ms": round(ms128, 4), "hpsi_gbps": round(gbs128, 1),
         "roofline": {"bound": "hbm", "achieved": round(gbs128, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(gbs128 / PEAK_HBM_GBS, 4),
@@ -361,21 +477,23 @@ def main():
             "hpsi_ms": round(ms64, 4), "hpsi_gbps": round(20.0 * (1 << n) / (ms64 * 1e-3) / 1e9, 1),
             "hpsi_frac": round(20.0 * (1 << n) / (ms64 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
             "infidelity_vs_c128": infid, "max_occ_err_vs_c128": float(np.abs(occ64 - occ).max()),
-            "krylov_iters_per_step": round(st64.krylov_iters / K, 3),
+            "krylov_iters_per_step": round(st64['krylov_iters'] / K, 3),
             "traffic": pmc_traffic("c64"),
         }
         rsv.rsv_register_destroy(reg64)
         del psi64
     del psi128
     torch.cuda.empty_cache()
+    if args.n30_steps > 0:
+        out["n30_c64"] = capacity_leg(rsv, wl, ctx, args.n30_steps)
     if args.serve_jobs > 0:
         out["serving"] = serving_leg(rsv, wl, ctx, args.serve_jobs, args.lanes)
-        out["serving"]["small_jobs"] = small_job_leg(rsv, wl, ctx, 4 * args.serve_jobs, args.lanes)
+        out["serving"]["small_jobs"] = small_job_leg(rsv, wl, ctx, 160, args.lanes)
     rsv.rsv_ctx_destroy(ctx)
 
     if not args.no_cpu:
-        log("cpu baseline: oracle H|psi> at N=27 ...")
-        out["cpu_baseline"] = cpu_baseline(w, iters_per_step)
+        log("cpu baseline: one oracle step at N=20 ...")
+        out["cpu_baseline"] = cpu_baseline(wl, round(iters_per_step, 2))
     log(f"total {time.perf_counter() - t0:.1f} s")
     print(json.dumps(out), flush=True)
 
