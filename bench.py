@@ -19,6 +19,7 @@ first (steps 0..W-1 from |0...0>), then K steps are timed (steps W..W+K-1).  Rep
   serving    the mixed-size stream: saturation solves/s, steady-state p50/p99 at 0.8 x
              saturation, the sequential complex128 plain path's rate and latencies, and the
              infidelity and occupation error of every served result against complex128,
+             and a shot-to-shot noise ensemble (512 members of the 10-atom chain),
   cpu_baseline  one time step of the CPU oracle, scaled to sim-us/s at 27 atoms.
 Every leg logs its progress to stderr at least every 20 s.
 """
@@ -318,6 +319,36 @@ def pmc_traffic(prec):
     return rec.get("bytes_per_application")
 
 
+def ensemble_leg(rsv, wl, ctx, members, lanes):
+    """Shot-to-shot noise ensemble of the 10-atom chain (constant drive, 1 us, dt = 10 ns):
+    `members` noisy copies (5 % drive amplitude, 2pi x 0.25 rad/us detuning per atom, 150 nm
+    positions), complex64, one shot each, packed by the server."""
+    w = wl.chain10()
+    srv = rsv.rsv_server_create(ctx, n_lanes=lanes, arena_bytes=2 << 30, pack_max_atoms=13)
+    try:
+        t0 = time.perf_counter()
+        rsv.rsv_server_submit_ensemble(srv, w.xyz, w.c6, rsv.PulseArrays(w.omega, w.delta),
+                                       rsv.evolve_opts(w.dt_ns, 1e-7, w.kmax, 12),
+                                       (0.05, 2 * np.pi * 0.25, 0.15), 9, members, "c64",
+                                       n_shots=1, seed=0)
+        done, prog = [], Progress("ensemble")
+        while len(done) < members:
+            done += rsv.rsv_server_poll(srv, 256, 1000)
+            prog(f"{len(done)} of {members} done")
+        span = time.perf_counter() - t0
+    finally:
+        rsv.rsv_server_destroy(srv)
+    assert all(c["status"] == 0 for c in done), done[0]["error"]
+    occ = np.mean([c["occupations"] for c in done], axis=0)
+    out = {"workload": "chain10 with shot-to-shot noise", "members": members,
+           "noise": {"omega_rel_sigma": 0.05, "delta_sigma_rad_per_us": 2 * np.pi * 0.25,
+                     "position_sigma_um": 0.15},
+           "precision": "complex64, packed", "member_solves_per_s": round(members / span, 2),
+           "ensemble_mean_occupations": [round(float(x), 5) for x in occ]}
+    log(f"ensemble: {members} members in {span:.2f} s ({out['member_solves_per_s']} solves/s)")
+    return out
+
+
 def capacity_leg(rsv, wl, ctx, steps):
     """The 5x6 triangular quench at 30 atoms in complex64 (FP64 Lanczos scalars and host
     tridiagonal exponential, kmax 20, dt = 5 ns): the first `steps` steps from |0...0>."""
@@ -489,6 +520,7 @@ def main():
     if args.serve_jobs > 0:
         out["serving"] = serving_leg(rsv, wl, ctx, args.serve_jobs, args.lanes)
         out["serving"]["small_jobs"] = small_job_leg(rsv, wl, ctx, 160, args.lanes)
+        out["serving"]["noise_ensemble"] = ensemble_leg(rsv, wl, ctx, 512, args.lanes)
     rsv.rsv_ctx_destroy(ctx)
 
     if not args.no_cpu:

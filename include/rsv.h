@@ -231,6 +231,26 @@ typedef struct {
   char error[160];
 } rsv_completion;
 
+/* Shot-to-shot parameter noise (Sec. III.A: open-system effects by varying the Hamiltonian's
+ * parameters from shot to shot).  Ensemble member s perturbs a job by standard normal
+ * variates g: the drive amplitude by one factor for all atoms, Omega_i(t) -> (1 +
+ * omega_rel_sigma g_0) Omega_i(t); each atom's detuning by a constant offset, delta_i(t) ->
+ * delta_i(t) + delta_sigma g_{1+i} (rad/us); each atom's position on each axis, r_{i,a} ->
+ * r_{i,a} + position_sigma_um g_{1+N+3i+a}.  Variate c = s (4N + 1) + j is the Box-Muller
+ * transform sqrt(-2 ln u1) cos(2 pi u2) of u1 = ((x_{2c} >> 11) + 1) 2^-53 and
+ * u2 = (x_{2c+1} >> 11) 2^-53, x_k the k-th output of SplitMix64 seeded with noise_seed. */
+typedef struct {
+  double omega_rel_sigma;   /* relative standard deviation of the drive amplitude */
+  double delta_sigma;       /* standard deviation of each atom's detuning offset, rad/us */
+  double position_sigma_um; /* standard deviation of each position coordinate, um */
+} rsv_noise;
+
+/* The perturbation of member s of an ensemble of n_atoms (host only): *omega_factor,
+ * delta_offset[n_atoms] (rad/us) and xyz_out[n_atoms][3] = xyz_um displaced (um). */
+int rsv_noise_member(const rsv_noise* noise, uint64_t noise_seed, int n_atoms, int64_t member,
+                     const double* xyz_um, double* omega_factor, double* delta_offset,
+                     double* xyz_out);
+
 int rsv_server_create(rsv_ctx* ctx, const rsv_server_opts* opts, rsv_server** out);
 /* Device bytes one job occupies in the arena. */
 size_t rsv_server_job_bytes(int n_atoms, int kmax, rsv_precision prec, int n_shots);
@@ -240,6 +260,14 @@ int rsv_server_submit(rsv_server* srv, const rsv_job_desc* job, uint64_t* job_id
 /* Waits up to timeout_ms (< 0: forever) for at least one completion and moves up to max of
  * them to out[0..*n_out). */
 int rsv_server_poll(rsv_server* srv, rsv_completion* out, int max, int* n_out, int timeout_ms);
+/* Queues n_members jobs, member s being `job` perturbed as rsv_noise_member(noise,
+ * noise_seed, n_atoms, s) describes (with delta_sigma > 0 the member's pulses become
+ * per-site).  Member s samples with seed job->seed + s and carries tag job->tag + s; its id
+ * goes to job_ids[s].  The members are queued together, in member order, so that small
+ * ones share packed launches; each is an ordinary job (alone == in the mix).  All or none
+ * are queued: RSV_EBUSY if the queue cannot take them all. */
+int rsv_server_submit_ensemble(rsv_server* srv, const rsv_job_desc* job, const rsv_noise* noise,
+                               uint64_t noise_seed, int n_members, uint64_t* job_ids);
 /* Frees the arrays of a polled completion. */
 void rsv_server_release(rsv_server* srv, rsv_completion* c);
 /* Cancels a queued job (it completes with RSV_ECANCELLED); RSV_EBUSY if it already runs,

@@ -11,13 +11,17 @@ emulator computes, written from the paper's statement of the method:
                      re-orthogonalisation (Sec. III.A).
 * ``observables`` -- occupations <n_i>, bitstring sampling with a SplitMix64 stream,
                      fidelity and energy.
+* ``noise``       -- shot-to-shot parameter noise of Sec. III.A: each ensemble member's
+                     perturbed drive amplitude, detunings and positions, drawn by a counter-
+                     based SplitMix64 stream and the Box-Muller transform.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
 may import this package.  The HIP library never calls into it and shares no code with it;
 the only shared module is the seeded input generator (``paper_2510_09813_amd.workloads``),
 which holds no arithmetic of the method.
 
-Parity status (what pins each public function in ``tests/test_oracle_pins.py``):
+Parity status (what pins each public function in ``tests/test_oracle_pins.py`` and
+``tests/test_noise.py``):
 * model.interaction_matrix, interaction_energy -- hand-computed pair energies and the
   all-excited state;
 * model.midpoint_sample, step_parameters -- the midpoint indices of Sec. III on a ramp and
@@ -34,6 +38,10 @@ Parity status (what pins each public function in ``tests/test_oracle_pins.py``):
   occupations -- product states; sample -- brute force of its definition and a chi-square
   test; fidelity_loss -- global phase, orthogonal and near-parallel vectors; energy --
   basis states and the two-level expectation value written out by hand.
+* noise.splitmix64_at -- the published SplitMix64 outputs; gaussian -- mean, variance and a
+  Kolmogorov-Smirnov test against the standard normal, no correlation between streams or
+  neighbours; member, member_pulses -- zero noise is the identity, perturbations scale
+  linearly with the standard deviations, the variate numbering.
 Every public function has a pin; none is "parity unpinned".
 """
-from . import model, evolve, observables  # noqa: F401
+from . import model, evolve, noise, observables  # noqa: F401

@@ -95,6 +95,13 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+// Shot-to-shot noise: standard normal variate c of the stream seeded with `seed`, and the
+// perturbation of ensemble member s (factor of Omega, per-atom detuning offsets [n],
+// displaced positions [n][3]).
+double noise_gaussian(uint64_t seed, uint64_t c);
+void noise_member(const rsv_noise& nz, uint64_t seed, int n, int64_t s, const double* xyz,
+                  double* factor, double* offsets, double* xyz_out);
+
 }  // namespace rsv
 
 struct rsv_ctx {

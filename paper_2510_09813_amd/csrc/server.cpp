@@ -528,42 +528,20 @@ void lane_main(rsv_server* srv) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-size_t rsv_server_job_bytes(int n, int kmax, rsv_precision prec, int shots) {
-  if (n < 1 || n > kMaxAtoms || kmax < 2 || kmax > kMaxKrylov || shots < 0) return 0;
-  return job_bytes(n, kmax, prec, shots);
-}
-
-int rsv_server_create(rsv_ctx* ctx, const rsv_server_opts* opts, rsv_server** out) {
-  if (!out) return fail(RSV_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!ctx || !opts) return fail(RSV_EINVAL, "NULL argument");
-  if (opts->n_lanes < 1 || opts->n_lanes > 16) return fail(RSV_EINVAL, "n_lanes must be in 1..16");
-  if (opts->max_queue < 0) return fail(RSV_EINVAL, "max_queue must be >= 0");
-  if (opts->pack_max_atoms < 0 || opts->pack_max_atoms > kMaxPackBits)
-    return fail(RSV_EINVAL, "pack_max_atoms must be in 0..%d", kMaxPackBits);
-  if (opts->pack_max_jobs < 0) return fail(RSV_EINVAL, "pack_max_jobs must be >= 0");
-  HIP_TRY(hipSetDevice(ctx->device));
-  size_t bytes = opts->arena_bytes;
-  if (bytes == 0) {
-    size_t free_b = 0, total_b = 0;
-    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    bytes = free_b / 4 * 3;
-  }
-  std::unique_ptr<rsv_server> s(new (std::nothrow) rsv_server());
-  if (!s) return fail(RSV_ENOMEM, "host allocation failed");
-  s->ctx = ctx;
-  s->opts = *opts;
-  RSV_TRY(s->arena.init(bytes));
-  s->t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < opts->n_lanes; ++i) s->lanes.emplace_back(lane_main, s.get());
-  *out = s.release();
+int check_noise(const rsv_noise* nz, int n, int64_t last_member) {
+  if (!(std::isfinite(nz->omega_rel_sigma) && nz->omega_rel_sigma >= 0.0 &&
+        std::isfinite(nz->delta_sigma) && nz->delta_sigma >= 0.0 &&
+        std::isfinite(nz->position_sigma_um) && nz->position_sigma_um >= 0.0))
+    return fail(RSV_EINVAL, "noise standard deviations must be finite and >= 0");
+  if (last_member < 0 || (uint64_t)last_member > (UINT64_MAX / 2 - 1) / (4 * (uint64_t)n + 1))
+    return fail(RSV_EINVAL, "member index out of range");
   return RSV_OK;
 }
 
-int rsv_server_submit(rsv_server* srv, const rsv_job_desc* jd, uint64_t* job_id) {
-  if (!srv || !jd) return fail(RSV_EINVAL, "NULL argument");
+// Validates and copies one job description (every array) into a Job.
+int make_job(rsv_server* srv, const rsv_job_desc* jd, std::unique_ptr<Job>* out) {
   const int n = jd->n_atoms;
   RSV_TRY(check_state_args(n, jd->prec));
   if (!jd->xyz_um) return fail(RSV_EINVAL, "positions are NULL");
@@ -608,18 +586,121 @@ int rsv_server_submit(rsv_server* srv, const rsv_job_desc* jd, uint64_t* job_id)
   if (j->bytes > srv->arena.capacity())
     return fail(RSV_ENOMEM, "job needs %zu bytes, the arena holds %zu", j->bytes,
                 srv->arena.capacity());
+  *out = std::move(j);
+  return RSV_OK;
+}
+
+// Queues jobs together, in order, or none of them; ids[i] receives job i's id.
+int enqueue(rsv_server* srv, std::vector<std::unique_ptr<Job>>& jobs, uint64_t* ids) {
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return fail(RSV_EINVAL, "server is shutting down");
-    if (srv->opts.max_queue > 0 && (int)srv->queue.size() >= srv->opts.max_queue)
+    if (srv->opts.max_queue > 0 &&
+        srv->queue.size() + jobs.size() > (size_t)srv->opts.max_queue)
       return fail(RSV_EBUSY, "queue full (%d jobs)", srv->opts.max_queue);
-    j->id = srv->next_id++;
-    j->t_submit = srv->now();
-    if (job_id) *job_id = j->id;
-    srv->queue.push_back(j.release());
+    const double t = srv->now();
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      jobs[i]->id = srv->next_id++;
+      jobs[i]->t_submit = t;
+      if (ids) ids[i] = jobs[i]->id;
+      srv->queue.push_back(jobs[i].release());
+    }
   }
-  srv->cv_work.notify_one();
+  if (jobs.size() == 1) srv->cv_work.notify_one();
+  else srv->cv_work.notify_all();
   return RSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rsv_server_job_bytes(int n, int kmax, rsv_precision prec, int shots) {
+  if (n < 1 || n > kMaxAtoms || kmax < 2 || kmax > kMaxKrylov || shots < 0) return 0;
+  return job_bytes(n, kmax, prec, shots);
+}
+
+int rsv_server_create(rsv_ctx* ctx, const rsv_server_opts* opts, rsv_server** out) {
+  if (!out) return fail(RSV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ctx || !opts) return fail(RSV_EINVAL, "NULL argument");
+  if (opts->n_lanes < 1 || opts->n_lanes > 16) return fail(RSV_EINVAL, "n_lanes must be in 1..16");
+  if (opts->max_queue < 0) return fail(RSV_EINVAL, "max_queue must be >= 0");
+  if (opts->pack_max_atoms < 0 || opts->pack_max_atoms > kMaxPackBits)
+    return fail(RSV_EINVAL, "pack_max_atoms must be in 0..%d", kMaxPackBits);
+  if (opts->pack_max_jobs < 0) return fail(RSV_EINVAL, "pack_max_jobs must be >= 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  size_t bytes = opts->arena_bytes;
+  if (bytes == 0) {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    bytes = free_b / 4 * 3;
+  }
+  std::unique_ptr<rsv_server> s(new (std::nothrow) rsv_server());
+  if (!s) return fail(RSV_ENOMEM, "host allocation failed");
+  s->ctx = ctx;
+  s->opts = *opts;
+  RSV_TRY(s->arena.init(bytes));
+  s->t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < opts->n_lanes; ++i) s->lanes.emplace_back(lane_main, s.get());
+  *out = s.release();
+  return RSV_OK;
+}
+
+int rsv_server_submit(rsv_server* srv, const rsv_job_desc* jd, uint64_t* job_id) {
+  if (!srv || !jd) return fail(RSV_EINVAL, "NULL argument");
+  std::vector<std::unique_ptr<Job>> one(1);
+  RSV_TRY(make_job(srv, jd, &one[0]));
+  return enqueue(srv, one, job_id);
+}
+
+int rsv_noise_member(const rsv_noise* nz, uint64_t seed, int n, int64_t s, const double* xyz,
+                     double* factor, double* offsets, double* xyz_out) {
+  if (!nz || !xyz || !factor || !offsets || !xyz_out) return fail(RSV_EINVAL, "NULL argument");
+  RSV_TRY(check_noise(nz, n, s));
+  noise_member(*nz, seed, n, s, xyz, factor, offsets, xyz_out);
+  return RSV_OK;
+}
+
+int rsv_server_submit_ensemble(rsv_server* srv, const rsv_job_desc* jd, const rsv_noise* nz,
+                               uint64_t noise_seed, int n_members, uint64_t* job_ids) {
+  if (!srv || !jd || !nz) return fail(RSV_EINVAL, "NULL argument");
+  if (n_members < 1) return fail(RSV_EINVAL, "n_members must be >= 1");
+  const int n = jd->n_atoms;
+  RSV_TRY(check_state_args(n, jd->prec));
+  if (!jd->xyz_um) return fail(RSV_EINVAL, "positions are NULL");
+  RSV_TRY(check_pulses(&jd->pulses, n));
+  RSV_TRY(check_noise(nz, n, n_members - 1));
+  const int64_t ns = jd->pulses.n_samples;
+  const bool site_in = jd->pulses.per_site != 0;
+  // detuning offsets make the pulses per-site; without them the member keeps the job's layout
+  const bool site_out = site_in || nz->delta_sigma != 0.0;
+  const size_t rows = site_out ? (size_t)n : 1;
+  std::vector<std::unique_ptr<Job>> jobs(n_members);
+  std::vector<double> xyz(3 * n), off(n), om(rows * ns), de(rows * ns), ph;
+  if (jd->pulses.phi) ph.resize(rows * ns);
+  for (int s = 0; s < n_members; ++s) {
+    double factor = 1.0;
+    noise_member(*nz, noise_seed, n, s, jd->xyz_um, &factor, off.data(), xyz.data());
+    for (size_t r = 0; r < rows; ++r) {
+      const size_t src = site_in ? r * ns : 0;
+      for (int64_t k = 0; k < ns; ++k) {
+        om[r * ns + k] = factor * jd->pulses.omega[src + k];
+        de[r * ns + k] = jd->pulses.delta[src + k] + (site_out ? off[r] : 0.0);
+        if (jd->pulses.phi) ph[r * ns + k] = jd->pulses.phi[src + k];
+      }
+    }
+    rsv_job_desc m = *jd;
+    m.xyz_um = xyz.data();
+    m.pulses.per_site = site_out ? 1 : 0;
+    m.pulses.omega = om.data();
+    m.pulses.delta = de.data();
+    m.pulses.phi = jd->pulses.phi ? ph.data() : nullptr;
+    m.seed = jd->seed + (uint64_t)s;
+    m.tag = jd->tag + (uint64_t)s;
+    RSV_TRY(make_job(srv, &m, &jobs[s]));  // copies every array
+  }
+  return enqueue(srv, jobs, job_ids);
 }
 
 int rsv_server_poll(rsv_server* srv, rsv_completion* out, int max, int* n_out, int timeout_ms) {

@@ -397,6 +397,11 @@ def _server_sigs(L):
         "rsv_server_status": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                         C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
         "rsv_server_destroy": (None, [vp]),
+        "rsv_noise_member": (C.c_int, [C.POINTER(Noise), C.c_uint64, C.c_int, C.c_int64,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "rsv_server_submit_ensemble": (C.c_int, [vp, C.POINTER(JobDesc), C.POINTER(Noise),
+                                                 C.c_uint64, C.c_int, C.POINTER(C.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -405,7 +410,13 @@ def _server_sigs(L):
 
 
 EXPORTED += ["rsv_server_create", "rsv_server_job_bytes", "rsv_server_submit", "rsv_server_poll",
-             "rsv_server_release", "rsv_server_cancel", "rsv_server_status", "rsv_server_destroy"]
+             "rsv_server_release", "rsv_server_cancel", "rsv_server_status", "rsv_server_destroy",
+             "rsv_noise_member", "rsv_server_submit_ensemble"]
+
+
+class Noise(C.Structure):
+    _fields_ = [("omega_rel_sigma", C.c_double), ("delta_sigma", C.c_double),
+                ("position_sigma_um", C.c_double)]
 
 
 def _slib():
@@ -441,6 +452,38 @@ def rsv_server_submit(srv, xyz, c6, pulses: PulseArrays, opts: EvolveOpts, preci
     jid = C.c_uint64()
     _check(_slib().rsv_server_submit(srv, C.byref(jd), C.byref(jid)))
     return int(jid.value)
+
+
+def rsv_noise_member(noise, noise_seed: int, xyz, member: int):
+    """(omega factor, delta offsets [N], displaced positions [N, 3]) of ensemble member
+    `member`; noise is (omega_rel_sigma, delta_sigma, position_sigma_um)."""
+    xyz = _f64(xyz).reshape(-1, 3)
+    n = xyz.shape[0]
+    f = C.c_double()
+    off, pos = np.empty(n), np.empty((n, 3))
+    pd = C.POINTER(C.c_double)
+    _check(_slib().rsv_noise_member(C.byref(Noise(*noise)), noise_seed, n, member,
+                                    xyz.ctypes.data_as(pd), C.byref(f), off.ctypes.data_as(pd),
+                                    pos.ctypes.data_as(pd)))
+    return f.value, off, pos
+
+
+def rsv_server_submit_ensemble(srv, xyz, c6, pulses: PulseArrays, opts: EvolveOpts, noise,
+                               noise_seed: int, n_members: int, precision="c64", psi0=None,
+                               n_shots: int = 0, seed: int = 0, return_state: bool = False,
+                               tag: int = 0):
+    """Queues n_members noisy copies of a job; returns their ids (member order)."""
+    xyz = _f64(xyz).reshape(-1, 3)
+    _check_pulses(pulses, xyz.shape[0])
+    buf = None if psi0 is None else _host_state(psi0, xyz.shape[0])
+    jd = JobDesc(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), float(c6),
+                 PRECISIONS.get(precision, precision), pulses.struct, opts,
+                 buf.ctypes.data if buf is not None else None, n_shots, seed, int(return_state), tag)
+    ids = np.zeros(max(int(n_members), 0), dtype=np.uint64)
+    _check(_slib().rsv_server_submit_ensemble(srv, C.byref(jd), C.byref(Noise(*noise)), noise_seed,
+                                              int(n_members),
+                                              ids.ctypes.data_as(C.POINTER(C.c_uint64))))
+    return [int(i) for i in ids]
 
 
 def rsv_server_poll(srv, max_n: int = 64, timeout_ms: int = -1):
