@@ -148,6 +148,15 @@ int rsv_apply_hamiltonian(rsv_register* reg, const rsv_pulses* pulses, int64_t s
 int rsv_evolve_device(rsv_register* reg, const rsv_pulses* pulses, const rsv_evolve_opts* opts,
                       void* d_psi_inout, void* hip_stream, rsv_stats* stats_out);
 
+/* rsv_evolve_device that also records <n_i> along the way (observables at intermediate
+ * times, Sec. IV): after every `every`-th step j (j = every, 2 every, ... <= the steps
+ * taken) the occupations of the new state go to occ_out[(j / every - 1) * n_atoms + i],
+ * accumulated (FP64) by the same pass that forms the state from the Krylov basis, so they
+ * cost no extra read of it.  occ_out: host, floor(steps / every) * n_atoms doubles. */
+int rsv_evolve_device_observed(rsv_register* reg, const rsv_pulses* pulses,
+                               const rsv_evolve_opts* opts, void* d_psi_inout, void* hip_stream,
+                               int every, double* occ_out, rsv_stats* stats_out);
+
 /* Host-level form: psi0_host is 2^N complex128 values (NULL = |0...0>); the result keeps
  * the evolved state on the device until rsv_result_destroy. */
 int rsv_evolve(rsv_register* reg, const rsv_pulses* pulses, const rsv_evolve_opts* opts,
@@ -163,11 +172,21 @@ int rsv_result_sample(const rsv_result* res, uint64_t seed, int n_shots, uint64_
 int rsv_result_stats(const rsv_result* res, rsv_stats* out);
 void rsv_result_destroy(rsv_result* res);
 
+/* <H_k> = <psi|H_k|psi> / <psi|psi> for the Hamiltonian of step `step` (eq. 3 with the
+ * midpoint parameters of Sec. III), from one H psi (the kernels of rsv_apply_hamiltonian)
+ * with FP64 inner products.  d_psi: 2^N amplitudes of the register's precision. */
+int rsv_energy_device(rsv_register* reg, const rsv_pulses* pulses, int64_t step, int dt_ns,
+                      const void* d_psi, double* energy_out, void* hip_stream);
+
 /* The same outputs for a caller device state of n_atoms in precision prec. */
 int rsv_occupations_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
                            double* n_out, void* hip_stream);
 int rsv_sample_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
                       uint64_t seed, int n_shots, uint64_t* idx_out, void* hip_stream);
+/* Correlators <n_i n_j> = sum_b |psi_b|^2 n_i(b) n_j(b) / |psi|^2 (Sec. IV's expectation
+ * values), FP64: out[i * n_atoms + j], symmetric, diagonal <n_i>. */
+int rsv_correlations_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
+                            double* out, void* hip_stream);
 
 /* Allocation-free form of rsv_sample_device, for callers that cannot allocate device or
  * pinned memory (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -51,6 +51,21 @@ def occupations(psi) -> np.ndarray:
     return out
 
 
+def correlations(psi) -> np.ndarray:
+    """<n_i n_j> = sum_b |psi_b|^2 [atom i excited][atom j excited] / sum_b |psi_b|^2, as an
+    N x N matrix (diagonal: <n_i>)."""
+    p = probabilities(psi)
+    n = int(round(np.log2(p.size)))
+    t = p.reshape((2,) * n)
+    total = p.sum()
+    out = np.empty((n, n))
+    for i in range(n):
+        ti = np.take(t, [1], axis=i)
+        for j in range(n):
+            out[i, j] = np.take(ti, [1], axis=j).sum() / total if j != i else ti.sum() / total
+    return out
+
+
 def sample(psi, seed: int, shots: int) -> np.ndarray:
     """Basis indices (uint64) of ``shots`` samples of |psi_b|^2, in shot order."""
     p = probabilities(psi)

@@ -1,6 +1,7 @@
 // C ABI of librsv (include/rsv.h): argument checks and handle management around the engine.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -160,6 +161,81 @@ int rsv_evolve_device(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_
   const int rc = evolve(reg, pl, o, d_psi, as_stream(stream), &st);
   if (stats_out) *stats_out = st;
   return rc;
+}
+
+int rsv_evolve_device_observed(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_opts* o,
+                               void* d_psi, void* stream, int every, double* occ_out,
+                               rsv_stats* stats_out) {
+  if (!occ_out) return fail(RSV_EINVAL, "occ_out is NULL");
+  if (every < 1) return fail(RSV_EINVAL, "every must be >= 1");
+  rsv_stats st{};
+  const int rc = evolve(reg, pl, o, d_psi, as_stream(stream), &st, every, occ_out);
+  if (stats_out) *stats_out = st;
+  return rc;
+}
+
+int rsv_energy_device(rsv_register* reg, const rsv_pulses* pl, int64_t step, int dt_ns,
+                      const void* d_psi, double* energy, void* stream) {
+  if (!reg || !d_psi || !energy) return fail(RSV_EINVAL, "NULL argument");
+  RSV_TRY(check_pulses(pl, reg->n));
+  if (dt_ns < 1) return fail(RSV_EINVAL, "dt_ns must be >= 1");
+  const int64_t K = (pl->n_samples - 1) / dt_ns;
+  if (step < 0 || step >= K)
+    return fail(RSV_EINVAL, "step %lld outside the pulse (%lld steps)", (long long)step,
+                (long long)K);
+  HIP_TRY(hipSetDevice(reg->ctx->device));
+  const int n = reg->n, prec = reg->prec;
+  const TilePlan plan = make_tile_plan(prec, n);
+  if (plan.n_hi_passes > 0 && !reg->d_hbuf)
+    RSV_TRY(reg->alloc->alloc(vec_bytes(n, prec), &reg->d_hbuf));
+  // H psi, the partial sums of Re<psi, H psi> and of |psi|^2, their two sums
+  const size_t vb = (vec_bytes(n, prec) + 255) / 256 * 256;
+  const int64_t np_dot = sweep_dot_partials(prec, n), np_norm = vec_num_partials(prec, n);
+  const size_t bytes = vb + (size_t)(np_dot + np_norm + 2) * sizeof(double);
+  void* blk = nullptr;
+  RSV_TRY(reg->alloc->alloc(bytes, &blk));
+  hipStream_t s = as_stream(stream);
+  double* pdot = (double*)((char*)blk + vb);
+  double* pnorm = pdot + np_dot;
+  double* res = pnorm + np_norm;
+  const StepCoef c = step_coef(pl, n, step, dt_ns);
+  const SweepIn in{d_psi, nullptr, nullptr, 1.0, 0.0, 0.0, nullptr, 0.0};
+  const SweepOut so{nullptr, nullptr, pdot};
+  hipError_t e = hpsi_sweep(prec, n, c, reg->d_dtab, in, blk, reg->d_hbuf, so, kAllPasses, s);
+  if (e == hipSuccess) e = finalize_sum(pdot, np_dot, res, s);
+  if (e == hipSuccess) e = norm2_partial(prec, n, d_psi, pnorm, s);
+  if (e == hipSuccess) e = finalize_sum(pnorm, np_norm, res + 1, s);
+  double h[2] = {0.0, 0.0};
+  if (e == hipSuccess) e = hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipStreamSynchronize(s);
+  reg->alloc->release(blk, bytes);
+  if (e != hipSuccess) return fail(RSV_EDEVICE, "energy: %s", hipGetErrorString(e));
+  if (!(h[1] > 0.0)) return fail(RSV_ENUMERIC, "state has zero norm");
+  *energy = h[0] / h[1];
+  return RSV_OK;
+}
+
+int rsv_correlations_device(rsv_ctx* ctx, int n, rsv_precision prec, const void* d_psi,
+                            double* out, void* stream) {
+  RSV_TRY(check_state_args(n, prec));
+  if (!ctx || !d_psi || !out) return fail(RSV_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  Scratch sc(ctx);
+  RSV_TRY(sc.get((size_t)corr_scratch_doubles(n) * sizeof(double)));
+  hipStream_t s = as_stream(stream);
+  double* dev = nullptr;
+  HIP_TRY(correlations(prec, n, d_psi, (double*)sc.p, &dev, s));
+  std::vector<double> h(1 + (size_t)n * n);
+  HIP_TRY(hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!(h[0] > 0.0)) return fail(RSV_ENUMERIC, "state has zero norm");
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const int p = std::min(n - 1 - i, n - 1 - j), q = std::max(n - 1 - i, n - 1 - j);
+      out[i * n + j] = h[1 + p * n + q] / h[0];
+    }
+  return RSV_OK;
 }
 
 int rsv_evolve(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_opts* o,

@@ -358,6 +358,7 @@ struct Lanczos {
   double alpha[kMaxKrylov + 1], beta[kMaxKrylov + 1], scale[kMaxKrylov + 1];
   double yre[kMaxKrylov], yim[kMaxKrylov];
   std::vector<double> work;
+  double* occ_partial = nullptr;  // fused occupation sums of an observed step's combination
 };
 
 // Device scalar slots [first_slot, first_slot + count) through the same slots of h_scal.
@@ -435,8 +436,10 @@ int last_component(Lanczos& L, int m, double h, double* out) {
 // (= H v_{k-1} - alpha_{k-1} v_{k-1} - beta_{k-2} v_{k-2}) in its first pass, stores it,
 // and returns |u_k|^2 = beta_{k-1}^2; the host then tests convergence of the m = k
 // dimensional Krylov approximation before the later passes compute z_k = H u_k.
+// With obs set, the combination that completes the step also writes the occupation sums of
+// the new state to obs (device, n + 1 doubles).
 int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, int max_depth,
-              bool reorth) {
+              bool reorth, double* obs = nullptr) {
   rsv_register* reg = L.reg;
   Workspace& ws = reg->ws;
   const int n = reg->n, prec = reg->prec;
@@ -562,7 +565,10 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
       cc.im[l] = nrm * L.yim[l] * L.scale[l];
       cc.x[l] = ws.basis[l];
     }
-    HIP_TRY(krylov_combine(prec, n, cc, ws.z, ws.pnorm, L.s));
+    if (obs && sub == remaining)
+      HIP_TRY(krylov_combine_occ(prec, n, cc, ws.z, ws.pnorm, L.occ_partial, obs, L.s));
+    else
+      HIP_TRY(krylov_combine(prec, n, cc, ws.z, ws.pnorm, L.s));
     HIP_TRY(finalize_sum(ws.pnorm, vec_num_partials(prec, n), ws.dscal + kNormSlot, L.s));
     std::swap(ws.basis[0], ws.z);
     RSV_TRY(fetch_scalars(L, kNormSlot, 1, &L.norm2));
@@ -573,13 +579,33 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
 
 }  // namespace
 
+namespace {
+
+// Device memory borrowed from an allocator for the duration of one call.
+struct Borrowed {
+  Allocator* a = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  ~Borrowed() {
+    if (p) {
+      (void)hipStreamSynchronize(s);
+      a->release(p, bytes);
+    }
+  }
+};
+
+}  // namespace
+
 int evolve(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_opts* o, void* d_psi,
-           hipStream_t s, rsv_stats* st) {
+           hipStream_t s, rsv_stats* st, int obs_every, double* obs_out) {
   if (!reg) return fail(RSV_EINVAL, "register is NULL");
   if (!d_psi) return fail(RSV_EINVAL, "state pointer is NULL");
   RSV_TRY(check_pulses(pl, reg->n));
   int64_t first = 0, count = 0;
   RSV_TRY(check_opts(o, pl, &first, &count));
+  if (obs_out && obs_every < 1) return fail(RSV_EINVAL, "observation interval must be >= 1");
+  const int64_t n_obs = obs_out ? count / obs_every : 0;
   const auto t0 = std::chrono::steady_clock::now();
   HIP_TRY(hipSetDevice(reg->ctx->device));
   RSV_TRY(workspace_acquire(reg, o->kmax));
@@ -598,14 +624,38 @@ int evolve(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_opts* o, vo
   std::memset(L.scale, 0, sizeof L.scale);
   L.work.assign(tridiag_work_doubles(kMaxKrylov), 0.0);
   RSV_TRY(fetch_scalars(L, kNormSlot, 1, &L.norm2));
+  // observed steps: fused occupation partials, then n + 1 sums per observation
+  Borrowed ob;
+  double* obs_dev = nullptr;
+  if (n_obs > 0) {
+    const size_t part = (size_t)combine_occ_partial_doubles(n);
+    ob.a = reg->alloc;
+    ob.s = s;
+    ob.bytes = (part + (size_t)n_obs * (n + 1)) * sizeof(double);
+    RSV_TRY(reg->alloc->alloc(ob.bytes, &ob.p));
+    L.occ_partial = (double*)ob.p;
+    obs_dev = L.occ_partial + part;
+  }
   const double tau = o->dt_ns * 1e-3;  // us
   for (int64_t k = first; k < first + count; ++k) {
     const StepCoef c = step_coef(pl, n, k, o->dt_ns);
-    RSV_TRY(propagate(L, c, tau, o->tol, o->kmax, o->max_substep_depth, o->reorth != 0));
+    const int64_t j = k - first + 1;  // steps done after this one
+    double* slot = (n_obs > 0 && j % obs_every == 0) ? obs_dev + (j / obs_every - 1) * (n + 1)
+                                                      : nullptr;
+    RSV_TRY(propagate(L, c, tau, o->tol, o->kmax, o->max_substep_depth, o->reorth != 0, slot));
     st->steps += 1;
   }
   HIP_TRY(hipMemcpyAsync(d_psi, ws.basis[0], vb, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (n_obs > 0) {
+    std::vector<double> h((size_t)n_obs * (n + 1));
+    HIP_TRY(hipMemcpy(h.data(), obs_dev, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < n_obs; ++r) {
+      const double* v = h.data() + r * (n + 1);
+      if (!(v[0] > 0.0)) return fail(RSV_ENUMERIC, "observed state has zero norm");
+      for (int i = 0; i < n; ++i) obs_out[r * n + i] = v[1 + (n - 1 - i)] / v[0];
+    }
+  }
   st->norm_final = std::sqrt(L.norm2);
   st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return RSV_OK;

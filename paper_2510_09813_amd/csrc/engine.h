@@ -150,8 +150,10 @@ void register_destroy(rsv_register* reg, hipStream_t stream);
 int workspace_acquire(rsv_register* reg, int kmax);
 
 // Evolves d_psi (2^n amplitudes of the register's precision) in place on `stream`.
+// With obs_out set, <n_i> of the state after every obs_every-th step are written to
+// obs_out[(j / obs_every - 1) * n + i] (host), accumulated by the pass that forms the state.
 int evolve(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_opts* o, void* d_psi,
-           hipStream_t stream, rsv_stats* st);
+           hipStream_t stream, rsv_stats* st, int obs_every = 0, double* obs_out = nullptr);
 
 // <n_i> and samples of a device state; d_scratch needs occupation_scratch_bytes /
 // sample_scratch_bytes; h_tmp is pinned host memory of at least 64 doubles.

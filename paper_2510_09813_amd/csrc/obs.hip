@@ -79,6 +79,125 @@ __global__ __launch_bounds__(kBlock) void occ_finalize_kernel(const double* __re
   }
 }
 
+// --------------------------------------------------------------------------- correlations
+// <n_i n_j> numerators.  Per chunk of 2^C amplitudes (C = min(n, 12)) the low C bits vary and
+// the bits above are constant, so a chunk contributes its total T, its single-bit sums S_p
+// (p < C) and its pair sums P_pq (p < q < C); pairs involving high bits follow from T and
+// S_p and the chunk index.  Thread t holds 16 amplitudes e = t + 256 s: bits 0..7 of e are
+// t's, bits 8..11 are s's.  Each thread keeps its total, its sums over the s bits and over
+// pairs of s bits; the 79 chunk values are then sums over threads in a fixed order.
+constexpr int kCorrSlots = 1 + 12 + 66;
+
+__device__ __forceinline__ int corr_pair_slot(int p, int q) {  // p < q < 12
+  return 13 + p * 12 - p * (p + 1) / 2 + (q - p - 1);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void corr_partial_kernel(const Cx<R>* __restrict__ x,
+                                                              const int cbits,
+                                                              double* __restrict__ partial) {
+  __shared__ double th[11][kBlock];  // total, 4 s-bit sums, 6 s-bit pair sums per thread
+  const uint32_t tid = threadIdx.x;
+  const uint32_t chunk = 1u << cbits;
+  const size_t base = (size_t)blockIdx.x << cbits;
+  double v[11];
+#pragma unroll
+  for (int j = 0; j < 11; ++j) v[j] = 0.0;
+  for (int s = 0; s < 16; ++s) {
+    const uint32_t e = tid + kBlock * s;
+    if (e >= chunk) break;
+    const double p = prob<R>(x[base + e]);
+    v[0] += p;
+    int j = 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if ((s >> q) & 1) v[1 + q] += p;
+#pragma unroll
+      for (int r = q + 1; r < 4; ++r, ++j)
+        if (((s >> q) & 1) && ((s >> r) & 1)) v[j] += p;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 11; ++j) th[j][tid] = v[j];
+  __syncthreads();
+  if (tid < kCorrSlots) {
+    // which per-thread value, and which thread bits must be set, for slot tid
+    int src = 0, ta = -1, tb = -1;
+    const int slot = (int)tid;
+    if (slot == 0) {
+      src = 0;
+    } else if (slot < 13) {  // single bit p
+      const int p = slot - 1;
+      if (p < 8) ta = p;
+      else src = 1 + (p - 8);
+    } else {  // pair p < q
+      int p = 0, q = 1;
+      for (int a = 0; a < 12; ++a)
+        for (int b = a + 1; b < 12; ++b)
+          if (corr_pair_slot(a, b) == slot) p = a, q = b;
+      if (q < 8) {
+        ta = p, tb = q;
+      } else if (p < 8) {
+        ta = p, src = 1 + (q - 8);
+      } else {
+        const int a = p - 8, b = q - 8;  // s-bit pair index in the order the loop above used
+        int j = 5;
+        for (int qq = 0; qq < 4; ++qq)
+          for (int rr = qq + 1; rr < 4; ++rr, ++j)
+            if (qq == a && rr == b) src = j;
+      }
+    }
+    double acc = 0.0;
+    for (int t = 0; t < kBlock; ++t) {
+      if (ta >= 0 && !((t >> ta) & 1)) continue;
+      if (tb >= 0 && !((t >> tb) & 1)) continue;
+      acc += th[src][t];
+    }
+    partial[(size_t)blockIdx.x * kCorrSlots + slot] = acc;
+  }
+}
+
+// out[0] = total; out[1 + p * n + q] (p <= q, bit positions) = sum |x_b|^2 b_p b_q.  One
+// workgroup per output; thread t sums chunks t, t + 256, ... then a fixed tree.
+__global__ __launch_bounds__(kBlock) void corr_finalize_kernel(const double* __restrict__ partial,
+                                                               const int64_t nchunk, const int n,
+                                                               const int cbits,
+                                                               double* __restrict__ out) {
+  __shared__ double red[4];
+  int p = -1, q = -1;  // workgroup 0: the total
+  if (blockIdx.x > 0) {
+    int w = (int)blockIdx.x - 1;
+    for (int a = 0; a < n && p < 0; ++a)
+      for (int b = a; b < n; ++b, --w)
+        if (w == 0) {
+          p = a, q = b;
+          break;
+        }
+  }
+  double acc = 0.0;
+  for (int64_t ch = threadIdx.x; ch < nchunk; ch += kBlock) {
+    const double* c = partial + ch * kCorrSlots;
+    double v;
+    if (p < 0) {
+      v = c[0];
+    } else if (p == q) {
+      v = p < cbits ? c[1 + p] : (((ch >> (p - cbits)) & 1) ? c[0] : 0.0);
+    } else if (q < cbits) {
+      v = c[corr_pair_slot(p, q)];
+    } else if (p < cbits) {
+      v = ((ch >> (q - cbits)) & 1) ? c[1 + p] : 0.0;
+    } else {
+      v = (((ch >> (p - cbits)) & 1) && ((ch >> (q - cbits)) & 1)) ? c[0] : 0.0;
+    }
+    acc += v;
+  }
+  const double t = block_sum_256(acc, red);
+  if (threadIdx.x == 0) {
+    if (p < 0) out[0] = t;
+    else out[1 + p * n + q] = t;
+  }
+}
+
 // ------------------------------------------------------------------------------- sampling
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t s) {
   uint64_t z = seed + (s + 1) * 0x9E3779B97F4A7C15ull;
@@ -265,6 +384,28 @@ hipError_t occupations(int prec, int n, const void* x, double* partial, double* 
                        (const float2*)x, cbits, partial);
   hipLaunchKernelGGL(occ_finalize_kernel, dim3(1), dim3(kBlock), 0, s, partial,
                      (int64_t)nchunk, n, cbits, out);
+  return hipGetLastError();
+}
+
+int64_t corr_scratch_doubles(int n) {
+  const int cbits = n < kChunkBits ? n : kChunkBits;
+  return (int64_t(1) << (n - cbits)) * kCorrSlots + 1 + (int64_t)n * n;
+}
+
+hipError_t correlations(int prec, int n, const void* x, double* scratch, double** out_dev,
+                        hipStream_t s) {
+  const int cbits = n < kChunkBits ? n : kChunkBits;
+  const uint32_t nchunk = 1u << (n - cbits);
+  double* out = scratch + (size_t)nchunk * kCorrSlots;
+  if (prec == kC128)
+    hipLaunchKernelGGL(corr_partial_kernel<double>, dim3(nchunk), dim3(kBlock), 0, s,
+                       (const double2*)x, cbits, scratch);
+  else
+    hipLaunchKernelGGL(corr_partial_kernel<float>, dim3(nchunk), dim3(kBlock), 0, s,
+                       (const float2*)x, cbits, scratch);
+  hipLaunchKernelGGL(corr_finalize_kernel, dim3(1 + n * (n + 1) / 2), dim3(kBlock), 0, s, scratch,
+                     (int64_t)nchunk, n, cbits, out);
+  *out_dev = out;
   return hipGetLastError();
 }
 

@@ -118,6 +118,12 @@ int64_t vec_num_partials(int prec, int n);
 // out = sum_l coef_l x_l; partial ||out||^2.
 hipError_t krylov_combine(int prec, int n, const CombineCoef& c, void* out, double* partial,
                           hipStream_t s);
+// The same combination, also accumulating the occupation numerators of the new state in the
+// same pass: occ_out[0] = sum |out|^2, occ_out[1 + p] = sum over amplitudes with bit p set
+// (device, n + 1 doubles); occ_partial holds combine_occ_partial_doubles(n).
+int64_t combine_occ_partial_doubles(int n);
+hipError_t krylov_combine_occ(int prec, int n, const CombineCoef& c, void* out, double* partial,
+                              double* occ_partial, double* occ_out, hipStream_t s);
 // partial ||x||^2.
 hipError_t norm2_partial(int prec, int n, const void* x, double* partial, hipStream_t s);
 // dst[0] = sum of partial[0..count) in a fixed order (one workgroup).
@@ -137,6 +143,11 @@ int64_t occ_num_partials(int n);
 // <n_i> numerators and the total, FP64: out[0] = sum |x|^2, out[1 + p] = sum |x_b|^2 b_p.
 hipError_t occupations(int prec, int n, const void* x, double* partial, double* out,
                        hipStream_t s);
+// <n_p n_q> numerators by bit position: *out_dev (inside scratch) gets [0] = sum |x|^2 and
+// [1 + p n + q] for p <= q; scratch holds corr_scratch_doubles(n) doubles.
+int64_t corr_scratch_doubles(int n);
+hipError_t correlations(int prec, int n, const void* x, double* scratch, double** out_dev,
+                        hipStream_t s);
 int64_t sample_scratch_doubles(int n);
 // idx[s] for s < shots; scratch holds sample_scratch_doubles(n) doubles.
 hipError_t sample(int prec, int n, const void* x, uint64_t seed, int shots, double* scratch,

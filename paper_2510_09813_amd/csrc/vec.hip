@@ -11,6 +11,9 @@ namespace rsv {
 namespace {
 
 constexpr int kPerThread = 8;
+// loop bits of the fused occupation sums: at most n - 19 (30 atoms, 2048 workgroups)
+constexpr int kOccLoopBits = 11;
+constexpr int kOccCombSlots = 1 + 8 + kOccLoopBits;
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void combine_kernel(const CombineCoef c,
@@ -38,6 +41,85 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombineCoef c,
   }
   const double t = block_sum_256(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// The combination with the occupation sums of the new state fused in (observables at
+// intermediate times, read from the same pass that writes the state).  With the grid of
+// stream_grid, thread t of workgroup w visits i = w * 256 + t + k * stride (stride = grid * 256,
+// a power of two SB = log2(stride) bits): bits [0, 8) of i are the thread's, bits [8, SB) the
+// workgroup's, bits above SB the loop counter's.  Per workgroup it writes, at
+// partial[w * kOccCombSlots + ...]: [0] sum |x|^2, [1 + b] the sum over thread bit b, [9 + q]
+// the sum over loop bit q; the workgroup bits are resolved when finalising.
+template <class R>
+__global__ __launch_bounds__(kBlock) void combine_occ_kernel(const CombineCoef c,
+                                                             Cx<R>* __restrict__ out,
+                                                             double* __restrict__ partial,
+                                                             double* __restrict__ occ_partial,
+                                                             const size_t count, const int sb) {
+  __shared__ double red[4];
+  __shared__ const Cx<R>* ptr[kMaxCombine];
+  if (threadIdx.x < c.m) ptr[threadIdx.x] = (const Cx<R>*)c.x[threadIdx.x];
+  __syncthreads();
+  double acc = 0.0, tot = 0.0, loop[kOccLoopBits];
+#pragma unroll
+  for (int q = 0; q < kOccLoopBits; ++q) loop[q] = 0.0;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  size_t k = 0;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride, ++k) {
+    double re = 0.0, im = 0.0;
+    for (int l = 0; l < c.m; ++l) {
+      const Cx<R> xi = ptr[l][i];
+      re += c.re[l] * (double)xi.x - c.im[l] * (double)xi.y;
+      im += c.re[l] * (double)xi.y + c.im[l] * (double)xi.x;
+    }
+    Cx<R> r;
+    r.x = (R)re;
+    r.y = (R)im;
+    out[i] = r;
+    acc = norm_add(acc, (double)r.x, (double)r.y);
+    // the probability of the stored (rounded) amplitude, as the occupation kernel forms it
+    const double pr = norm_add(0.0, (double)r.x, (double)r.y);
+    tot += pr;
+#pragma unroll
+    for (int q = 0; q < kOccLoopBits; ++q)
+      if ((k >> q) & 1) loop[q] += pr;
+  }
+  const double t = block_sum_256(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  double* o = occ_partial + (size_t)blockIdx.x * kOccCombSlots;
+  const double all = block_sum_256(tot, red);
+  if (threadIdx.x == 0) o[0] = all;
+  for (int b = 0; b < 8; ++b) {
+    const double v = block_sum_256(((threadIdx.x >> b) & 1) ? tot : 0.0, red);
+    if (threadIdx.x == 0) o[1 + b] = v;
+  }
+  const int nloop = (int)(64 - __clzll((unsigned long long)((count - 1) | 1))) - sb;  // bits above SB
+  for (int q = 0; q < kOccLoopBits; ++q) {
+    if (q >= nloop) break;
+    const double v = block_sum_256(loop[q], red);
+    if (threadIdx.x == 0) o[9 + q] = v;
+  }
+}
+
+// <n> numerators of combine_occ_kernel's partials: out[0] = total, out[1 + p] = sum over
+// amplitudes with bit p set, p < n.  Fixed order: thread t sums workgroups t, t + 256, ...
+__global__ __launch_bounds__(kBlock) void combine_occ_finalize(const double* __restrict__ part,
+                                                               const int64_t nwg, const int n,
+                                                               const int sb,
+                                                               double* __restrict__ out) {
+  __shared__ double red[4];
+  for (int p = -1; p < n; ++p) {
+    double a = 0.0;
+    for (int64_t w = threadIdx.x; w < nwg; w += kBlock) {
+      const double* o = part + w * kOccCombSlots;
+      if (p < 0) a += o[0];
+      else if (p < 8) a += o[1 + p];
+      else if (p < sb) a += ((w >> (p - 8)) & 1) ? o[0] : 0.0;
+      else a += o[9 + (p - sb)];
+    }
+    const double t = block_sum_256(a, red);
+    if (threadIdx.x == 0) out[1 + p] = t;
+  }
 }
 
 template <class R>
@@ -132,6 +214,15 @@ __global__ __launch_bounds__(kBlock) void convert_kernel(const Cx<RS>* __restric
   }
 }
 
+int ilog2_u64(uint64_t v) {
+  int r = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++r;
+  }
+  return r;
+}
+
 }  // namespace
 
 int64_t vec_num_partials(int prec, int n) {
@@ -149,6 +240,27 @@ hipError_t krylov_combine(int prec, int n, const CombineCoef& c, void* out, doub
   else
     hipLaunchKernelGGL(combine_kernel<float>, dim3(g), dim3(kBlock), 0, s, c, (float2*)out,
                        partial, count);
+  return hipGetLastError();
+}
+
+int64_t combine_occ_partial_doubles(int n) {
+  return (int64_t)stream_grid(size_t(1) << n, kPerThread) * kOccCombSlots;
+}
+
+hipError_t krylov_combine_occ(int prec, int n, const CombineCoef& c, void* out, double* partial,
+                              double* occ_partial, double* occ_out, hipStream_t s) {
+  const size_t count = size_t(1) << n;
+  const uint32_t g = stream_grid(count, kPerThread);
+  const int sb = ilog2_u64((uint64_t)g * kBlock);
+  if (n - sb > kOccLoopBits || n > kMaxAtoms) return hipErrorInvalidValue;
+  if (prec == kC128)
+    hipLaunchKernelGGL(combine_occ_kernel<double>, dim3(g), dim3(kBlock), 0, s, c,
+                       (double2*)out, partial, occ_partial, count, sb);
+  else
+    hipLaunchKernelGGL(combine_occ_kernel<float>, dim3(g), dim3(kBlock), 0, s, c,
+                       (float2*)out, partial, occ_partial, count, sb);
+  hipLaunchKernelGGL(combine_occ_finalize, dim3(1), dim3(kBlock), 0, s, occ_partial,
+                     (int64_t)g, n, sb, occ_out);
   return hipGetLastError();
 }
 

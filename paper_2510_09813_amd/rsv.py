@@ -28,7 +28,8 @@ EXPORTED = [
     "rsv_apply_hamiltonian", "rsv_evolve_device", "rsv_evolve", "rsv_result_state",
     "rsv_result_occupations", "rsv_result_sample", "rsv_result_stats", "rsv_result_destroy",
     "rsv_occupations_device", "rsv_sample_device", "rsv_sample_device_static",
-    "rsv_tridiag_expm",
+    "rsv_tridiag_expm", "rsv_evolve_device_observed", "rsv_energy_device",
+    "rsv_correlations_device",
 ]
 
 
@@ -100,6 +101,10 @@ def lib():
         "rsv_sample_device_static": (i32, [vp, i32, i32, vp, u64, i32, C.POINTER(C.c_uint64),
                                            vp]),
         "rsv_tridiag_expm": (i32, [i32, pd, pd, dbl, pd, pd]),
+        "rsv_evolve_device_observed": (i32, [vp, C.POINTER(Pulses), C.POINTER(EvolveOpts), vp,
+                                             vp, i32, pd, C.POINTER(Stats)]),
+        "rsv_energy_device": (i32, [vp, C.POINTER(Pulses), i64, i32, vp, pd, vp]),
+        "rsv_correlations_device": (i32, [vp, i32, i32, vp, pd, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -273,6 +278,35 @@ def rsv_evolve_device(reg: Register, pulses: PulseArrays, opts: EvolveOpts, d_ps
     return st
 
 
+def rsv_evolve_device_observed(reg: Register, pulses: PulseArrays, opts: EvolveOpts, d_psi,
+                               every: int, stream=None):
+    """Evolves d_psi in place; returns (stats, occupations [steps // every, N]) where row r
+    holds <n_i> after step (r + 1) * every of the call."""
+    _check_pulses(pulses, reg.n_atoms)
+    if every < 1:
+        raise ValueError("every must be >= 1")
+    ptr = _state_ptr(d_psi, reg.n_atoms, reg.precision, "state")
+    total = (pulses.omega.shape[-1] - 1) // opts.dt_ns
+    first = opts.first_step
+    steps = total - first if opts.n_steps < 0 else min(opts.n_steps, total - first)
+    occ = np.zeros((max(steps, 0) // every, reg.n_atoms))
+    st = Stats()
+    _check(lib().rsv_evolve_device_observed(reg, C.byref(pulses.struct), C.byref(opts), ptr,
+                                            _stream(stream), every,
+                                            occ.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)))
+    return st, occ
+
+
+def rsv_energy_device(reg: Register, pulses: PulseArrays, step: int, dt_ns: int, d_psi,
+                      stream=None) -> float:
+    _check_pulses(pulses, reg.n_atoms)
+    ptr = _state_ptr(d_psi, reg.n_atoms, reg.precision, "state")
+    e = C.c_double()
+    _check(lib().rsv_energy_device(reg, C.byref(pulses.struct), step, dt_ns, ptr, C.byref(e),
+                                   _stream(stream)))
+    return e.value
+
+
 def rsv_evolve(reg: Register, pulses: PulseArrays, opts: EvolveOpts, psi0=None):
     _check_pulses(pulses, reg.n_atoms)
     h = C.c_void_p()
@@ -348,6 +382,15 @@ def rsv_sample_device_static(ctx, n_atoms: int, d_psi, seed: int, n_shots: int,
     _check(lib().rsv_sample_device_static(ctx, n, prec, ptr, seed, n_shots,
                                           out.ctypes.data_as(C.POINTER(C.c_uint64)),
                                           _stream(stream)))
+    return out
+
+
+def rsv_correlations_device(ctx, n_atoms: int, d_psi, precision="c128", stream=None) -> np.ndarray:
+    prec, n = _prec(precision), _atoms(n_atoms)
+    ptr = _state_ptr(d_psi, n, prec, "state")
+    out = np.empty((n, n), dtype=np.float64)
+    _check(lib().rsv_correlations_device(ctx, n, prec, ptr,
+                                         out.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
     return out
 
 

@@ -329,3 +329,26 @@ def test_energy_expectation():
     got = observables.energy(np.array([a, b]), lambda x: model.apply_hamiltonian(
         x, np.zeros((1, 1)), [o1], [d1], [p1]))
     assert got == pytest.approx(want, rel=1e-14)
+
+
+def test_correlations_pins():
+    """<n_i n_j>: basis states (0/1 products), a product state (<n_i n_j> = <n_i><n_j> off
+    the diagonal, <n_i> on it) and the two-atom blockade state (|01> + |10>)/sqrt(2), whose
+    pair correlator vanishes."""
+    n = 4
+    for b in (0, 5, 15, 9):
+        psi = np.zeros(1 << n, complex)
+        psi[b] = 1
+        lv = np.array(model.atom_levels(b, n), float)
+        np.testing.assert_array_equal(observables.correlations(psi), np.outer(lv, lv))
+    rng = np.random.default_rng(3)
+    singles = [rng.standard_normal(2) + 1j * rng.standard_normal(2) for _ in range(n)]
+    psi = singles[0]
+    for s_ in singles[1:]:
+        psi = np.kron(psi, s_)
+    q = np.array([abs(s_[1]) ** 2 / (abs(s_[0]) ** 2 + abs(s_[1]) ** 2) for s_ in singles])
+    want = np.outer(q, q)
+    np.fill_diagonal(want, q)
+    np.testing.assert_allclose(observables.correlations(psi), want, atol=1e-14)
+    w = np.array([0, 1, 1, 0]) / np.sqrt(2)
+    np.testing.assert_allclose(observables.correlations(w), [[0.5, 0.0], [0.0, 0.5]], atol=1e-15)
