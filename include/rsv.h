@@ -199,6 +199,35 @@ int rsv_correlations_device(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const
 int rsv_sample_device_static(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_psi,
                              uint64_t seed, int n_shots, uint64_t* idx_out, void* hip_stream);
 
+/* ------------------------------------------------------------------ open systems
+ * The Lindblad master equation (Sec. III.A: open-system dynamics by the full master
+ * equation, evolved with a Krylov method) on the vectorised density matrix:
+ *   d rho/dt = -i [H_k, rho] + sum_i (L_i rho L_i^+ - {L_i^+ L_i, rho}/2)
+ * with, per atom, relaxation of the Rydberg level L_i = sqrt(relax_rate) |0><1|_i and
+ * dephasing L_i = sqrt(2 dephasing_rate) n_i (an atom's coherences then decay at
+ * dephasing_rate; equivalently sqrt(dephasing_rate/2) sigma^z_i).  Rates in 1/us.
+ * rho is 2^N x 2^N, stored row-major as 4^N amplitudes of the register's precision,
+ * element (r, c) at index (r << N) | c with the state-vector bit order; N <= 14. */
+typedef struct {
+  double relax_rate;
+  double dephasing_rate;
+} rsv_lindblad;
+
+/* d_out = L_k d_in for step `step` (test and benchmark hook); returns after the stream finished. */
+int rsv_lindblad_apply(rsv_register* reg, const rsv_pulses* pulses, int64_t step, int dt_ns,
+                       const rsv_lindblad* rates, const void* d_in, void* d_out, void* hip_stream);
+/* rho <- exp(dt L_{k}) rho for the requested steps (opts as for rsv_evolve_device; reorth is
+ * ignored, kmax <= 63), each exponential by the Arnoldi process (two passes of classical
+ * Gram-Schmidt, FP64 inner products, host FP64 exponential of the Hessenberg matrix) to the
+ * estimate |rho| h_{m+1,m} |[exp(dt H_m) e_1]_m| <= tol, halving the step without
+ * convergence.  stats->norm_final is the Frobenius norm of the final rho. */
+int rsv_lindblad_evolve_device(rsv_register* reg, const rsv_pulses* pulses,
+                               const rsv_evolve_opts* opts, const rsv_lindblad* rates,
+                               void* d_rho_inout, void* hip_stream, rsv_stats* stats_out);
+/* <n_i> = sum_r rho_rr n_i(r) / Tr rho and Tr rho (trace_out may be NULL). */
+int rsv_lindblad_occupations(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_rho,
+                             double* occ_out, double* trace_out, void* hip_stream);
+
 /* ------------------------------------------------------------------ serving
  * A server evolves a stream of independent jobs (each a register, its pulses and options)
  * on one device with continuous batching: n_lanes jobs run at once, each on its own HIP

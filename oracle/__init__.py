@@ -11,6 +11,9 @@ emulator computes, written from the paper's statement of the method:
                      re-orthogonalisation (Sec. III.A).
 * ``observables`` -- occupations <n_i>, bitstring sampling with a SplitMix64 stream,
                      fidelity and energy.
+* ``lindblad``    -- the Lindblad master equation of Sec. III.A (open systems): the dense
+                     Liouvillian with per-atom relaxation and dephasing, stepped by scipy's
+                     matrix exponential.
 * ``noise``       -- shot-to-shot parameter noise of Sec. III.A: each ensemble member's
                      perturbed drive amplitude, detunings and positions, drawn by a counter-
                      based SplitMix64 stream and the Box-Muller transform.
@@ -20,8 +23,8 @@ may import this package.  The HIP library never calls into it and shares no code
 the only shared module is the seeded input generator (``paper_2510_09813_amd.workloads``),
 which holds no arithmetic of the method.
 
-Parity status (what pins each public function in ``tests/test_oracle_pins.py`` and
-``tests/test_noise.py``):
+Parity status (what pins each public function in ``tests/test_oracle_pins.py``,
+``tests/test_noise.py`` and ``tests/test_lindblad_oracle.py``):
 * model.interaction_matrix, interaction_energy -- hand-computed pair energies and the
   all-excited state;
 * model.midpoint_sample, step_parameters -- the midpoint indices of Sec. III on a ramp and
@@ -42,6 +45,9 @@ Parity status (what pins each public function in ``tests/test_oracle_pins.py`` a
   Kolmogorov-Smirnov test against the standard normal, no correlation between streams or
   neighbours; member, member_pulses -- zero noise is the identity, perturbations scale
   linearly with the standard deviations, the variate numbering.
+* lindblad.evolve, liouvillian, jump_operators, occupations -- no dissipation equals the
+  pure-state oracle, relaxation and dephasing closed forms, the optical Bloch steady state,
+  trace, Hermiticity and positivity.
 Every public function has a pin; none is "parity unpinned".
 """
-from . import model, evolve, noise, observables  # noqa: F401
+from . import model, evolve, lindblad, noise, observables  # noqa: F401

@@ -1,0 +1,111 @@
+// Liouvillian of the Lindblad master equation (Sec. III.A: open-system dynamics by the full
+// master equation, evolved with a Krylov method) on the vectorised density matrix.
+//
+//   d rho / dt = L rho = -i [H_k, rho] + sum_i (L_i rho L_i^+ - 1/2 {L_i^+ L_i, rho})
+//
+// with H_k the Hamiltonian of eq. (3) for step k and, per atom, relaxation of the Rydberg
+// level L_i = sqrt(gamma_r) |0><1|_i and dephasing L_i = sqrt(2 gamma_phi) n_i (coherences of
+// one atom decay at gamma_phi).  rho (2^n x 2^n) is stored row-major as a vector of 4^n
+// amplitudes, index (r << n) | c, so the row's bits are the high n bits of the index and the
+// column's the low n: bit p of r or c is atom n-1-p as in the state vector.  Element (r, c):
+//
+//   (L rho)_rc = [-i (D_r - D_c) - sum_p (gamma_r (r_p + c_p) / 2 + gamma_phi (r_p xor c_p))] rho_rc
+//              + sum_p [ -i h(r_p) rho_{r^p, c}  +  i h(1 - c_p) rho_{r, c^p} ]
+//              + gamma_r sum_{p: r_p = c_p = 0} rho_{r|p, c|p}
+//
+// where D_x = E_x - sum_p delta_p x_p is H's diagonal (E_x the interaction energy of pattern
+// x), h(1) = <1|h_p|0> = Omega_p/2 e^{-i phi_p} and h(0) = <0|h_p|1>.  One thread per element
+// gathers its 3n + 1 inputs through the cache (the 4^n vector is at most 4 GiB: n <= 14), all
+// arithmetic in FP64, stored in the storage precision.
+#include "device_common.h"
+#include "lindblad.h"
+
+namespace rsv {
+namespace {
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void liouvillian_kernel(const LindbladCoef c,
+                                                             const double* __restrict__ e,
+                                                             const Cx<R>* __restrict__ x,
+                                                             Cx<R>* __restrict__ y) {
+  const int n = c.n;
+  const uint64_t count = uint64_t(1) << (2 * n);
+  const uint32_t cmask = (1u << n) - 1u;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
+    const uint32_t r = (uint32_t)(idx >> n), col = (uint32_t)idx & cmask;
+    double dr = e[r], dc = e[col], loss = 0.0;
+    for (int p = 0; p < n; ++p) {
+      const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
+      dr -= rp ? c.delta[p] : 0.0;
+      dc -= cp ? c.delta[p] : 0.0;
+      loss += 0.5 * c.gamma_r * (double)(rp + cp) + ((rp ^ cp) ? c.gamma_phi : 0.0);
+    }
+    const Cx<R> v = x[idx];
+    // (-i (dr - dc) - loss) * v
+    double are = -loss * (double)v.x + (dr - dc) * (double)v.y;
+    double aim = -loss * (double)v.y - (dr - dc) * (double)v.x;
+    for (int p = 0; p < n; ++p) {
+      const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
+      // row flip: -i h(r_p) rho_{r^p, c}
+      const Cx<R> a = x[idx ^ (uint64_t(1) << (n + p))];
+      const double hr = rp ? c.up_re[p] : c.dn_re[p], hi = rp ? c.up_im[p] : c.dn_im[p];
+      // -i (hr + i hi)(a) = (hi a.x + hr a.y) + i (hi a.y - hr a.x)
+      are += hi * (double)a.x + hr * (double)a.y;
+      aim += hi * (double)a.y - hr * (double)a.x;
+      // column flip: +i h(1 - c_p) rho_{r, c^p}
+      const Cx<R> b = x[idx ^ (uint64_t(1) << p)];
+      const double gr = cp ? c.dn_re[p] : c.up_re[p], gi = cp ? c.dn_im[p] : c.up_im[p];
+      // i (gr + i gi)(b) = (-gi b.x - gr b.y) + i (gr b.x - gi b.y)
+      are += -gi * (double)b.x - gr * (double)b.y;
+      aim += gr * (double)b.x - gi * (double)b.y;
+      // relaxation feeds (0, 0) of atom p from (1, 1)
+      if (c.gamma_r != 0.0 && !rp && !cp) {
+        const Cx<R> q = x[idx | (uint64_t(1) << (n + p)) | (uint64_t(1) << p)];
+        are += c.gamma_r * (double)q.x;
+        aim += c.gamma_r * (double)q.y;
+      }
+    }
+    Cx<R> o;
+    o.x = (R)are;
+    o.y = (R)aim;
+    y[idx] = o;
+  }
+}
+
+// Diagonal of rho: out[r] = Re rho_rr (FP64), r < 2^n.
+template <class R>
+__global__ __launch_bounds__(kBlock) void rho_diag_kernel(const Cx<R>* __restrict__ x, const int n,
+                                                         double* __restrict__ out) {
+  const uint32_t dim = 1u << n;
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < dim; r += gridDim.x * blockDim.x)
+    out[r] = (double)x[((uint64_t)r << n) | r].x;
+}
+
+}  // namespace
+
+hipError_t liouvillian_apply(int prec, const LindbladCoef& c, const double* e, const void* x,
+                             void* y, hipStream_t s) {
+  const uint64_t count = uint64_t(1) << (2 * c.n);
+  uint64_t g = (count + kBlock - 1) / kBlock;
+  if (g > 8192) g = 8192;
+  if (prec == kC128)
+    hipLaunchKernelGGL(liouvillian_kernel<double>, dim3((uint32_t)g), dim3(kBlock), 0, s, c, e,
+                       (const double2*)x, (double2*)y);
+  else
+    hipLaunchKernelGGL(liouvillian_kernel<float>, dim3((uint32_t)g), dim3(kBlock), 0, s, c, e,
+                       (const float2*)x, (float2*)y);
+  return hipGetLastError();
+}
+
+hipError_t rho_diagonal(int prec, int n, const void* x, double* out, hipStream_t s) {
+  const uint32_t dim = 1u << n;
+  const uint32_t g = (dim + kBlock - 1) / kBlock;
+  if (prec == kC128)
+    hipLaunchKernelGGL(rho_diag_kernel<double>, dim3(g), dim3(kBlock), 0, s, (const double2*)x, n, out);
+  else
+    hipLaunchKernelGGL(rho_diag_kernel<float>, dim3(g), dim3(kBlock), 0, s, (const float2*)x, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace rsv

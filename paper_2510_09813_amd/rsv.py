@@ -29,8 +29,13 @@ EXPORTED = [
     "rsv_result_occupations", "rsv_result_sample", "rsv_result_stats", "rsv_result_destroy",
     "rsv_occupations_device", "rsv_sample_device", "rsv_sample_device_static",
     "rsv_tridiag_expm", "rsv_evolve_device_observed", "rsv_energy_device",
-    "rsv_correlations_device",
+    "rsv_correlations_device", "rsv_lindblad_apply", "rsv_lindblad_evolve_device",
+    "rsv_lindblad_occupations",
 ]
+
+
+class Lindblad(C.Structure):
+    _fields_ = [("relax_rate", C.c_double), ("dephasing_rate", C.c_double)]
 
 
 class RsvError(RuntimeError):
@@ -105,6 +110,11 @@ def lib():
                                              vp, i32, pd, C.POINTER(Stats)]),
         "rsv_energy_device": (i32, [vp, C.POINTER(Pulses), i64, i32, vp, pd, vp]),
         "rsv_correlations_device": (i32, [vp, i32, i32, vp, pd, vp]),
+        "rsv_lindblad_apply": (i32, [vp, C.POINTER(Pulses), i64, i32, C.POINTER(Lindblad), vp,
+                                     vp, vp]),
+        "rsv_lindblad_evolve_device": (i32, [vp, C.POINTER(Pulses), C.POINTER(EvolveOpts),
+                                             C.POINTER(Lindblad), vp, vp, C.POINTER(Stats)]),
+        "rsv_lindblad_occupations": (i32, [vp, i32, i32, vp, pd, pd, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -392,6 +402,41 @@ def rsv_correlations_device(ctx, n_atoms: int, d_psi, precision="c128", stream=N
     _check(lib().rsv_correlations_device(ctx, n, prec, ptr,
                                          out.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
     return out
+
+
+def _rho_ptr(buf, n_atoms: int, precision: int, what: str) -> int:
+    return _dptr(buf, 1 << (2 * n_atoms), COMPLEX_DTYPE[precision], what)
+
+
+def rsv_lindblad_apply(reg: Register, pulses: PulseArrays, step: int, dt_ns: int, rates, d_in,
+                       d_out, stream=None):
+    """d_out = L_step d_in; rates = (relax_rate, dephasing_rate) in 1/us."""
+    _check_pulses(pulses, reg.n_atoms)
+    pin = _rho_ptr(d_in, reg.n_atoms, reg.precision, "input density matrix")
+    pout = _rho_ptr(d_out, reg.n_atoms, reg.precision, "output density matrix")
+    _check(lib().rsv_lindblad_apply(reg, C.byref(pulses.struct), step, dt_ns,
+                                    C.byref(Lindblad(*rates)), pin, pout, _stream(stream)))
+
+
+def rsv_lindblad_evolve_device(reg: Register, pulses: PulseArrays, opts: EvolveOpts, rates, d_rho,
+                               stream=None) -> Stats:
+    _check_pulses(pulses, reg.n_atoms)
+    ptr = _rho_ptr(d_rho, reg.n_atoms, reg.precision, "density matrix")
+    st = Stats()
+    _check(lib().rsv_lindblad_evolve_device(reg, C.byref(pulses.struct), C.byref(opts),
+                                            C.byref(Lindblad(*rates)), ptr, _stream(stream),
+                                            C.byref(st)))
+    return st
+
+
+def rsv_lindblad_occupations(ctx, n_atoms: int, d_rho, precision="c128", stream=None):
+    """(<n_i> [N], trace) of a device density matrix."""
+    prec, n = _prec(precision), _atoms(n_atoms)
+    ptr = _rho_ptr(d_rho, n, prec, "density matrix")
+    out, tr = np.empty(n), C.c_double()
+    _check(lib().rsv_lindblad_occupations(ctx, n, prec, ptr, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                          C.byref(tr), _stream(stream)))
+    return out, tr.value
 
 
 def rsv_tridiag_expm(alpha, beta, tau: float):

@@ -1,0 +1,95 @@
+"""Pins of the oracle's Lindblad evolution (oracle/lindblad.py) and of the library's host
+exponential of a dense matrix (the Hessenberg step of its Arnoldi exponential), CPU only."""
+import ctypes as C
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from oracle import evolve, lindblad, model
+from paper_2510_09813_amd import rsv
+from paper_2510_09813_amd import workloads as wl
+
+
+def pure(psi):
+    return np.outer(psi, psi.conj())
+
+
+def test_no_dissipation_is_the_pure_state_evolution():
+    rng = np.random.default_rng(1)
+    n, t_ns = 3, 200
+    xyz = wl.random_register(n, 15.0, 5.0, rng)
+    om = np.outer(rng.uniform(0.5, 1.5, n), wl.pwl([0, 100, 200], [0, 12, 3], t_ns))
+    de = np.outer(rng.uniform(0.5, 1.5, n), wl.pwl([0, 200], [-8, 9], t_ns))
+    ph = np.outer(rng.uniform(-1, 1, n), np.linspace(0, 1, t_ns + 1))
+    psi0 = wl.random_state(n, rng)
+    rho = lindblad.evolve(xyz, wl.C6_RB, om, de, ph, t_ns, 10, pure(psi0), 0.0, 0.0)
+    psi = evolve.evolve(xyz, wl.C6_RB, om, de, ph, t_ns, 10, psi0=psi0, method="dense")
+    np.testing.assert_allclose(rho, pure(psi), atol=1e-12)
+
+
+def test_relaxation_closed_form():
+    """Omega = 0: each excited atom decays as exp(-gamma t), interactions or not."""
+    g, t_ns = 1.7, 500
+    xyz = wl.chain(2, 5.0)
+    z = np.zeros(t_ns + 1)
+    rho0 = np.zeros((4, 4), complex)
+    rho0[3, 3] = 1.0  # |11>
+    rho = lindblad.evolve(xyz, wl.C6_RB, z, z + 3.0, None, t_ns, 10, rho0, g, 0.0)
+    t = t_ns * 1e-3
+    np.testing.assert_allclose(lindblad.occupations(rho), np.exp(-g * t) * np.ones(2), rtol=1e-12)
+    assert abs(rho[3, 3].real - np.exp(-2 * g * t)) < 1e-13
+    assert abs(np.trace(rho) - 1) < 1e-13
+
+
+def test_dephasing_closed_form():
+    """One atom in (|0> + |1>)/sqrt(2), Omega = 0, detuning delta: the coherence rho_01
+    rotates as exp(-i delta t) and decays as exp(-gamma_phi t)."""
+    gphi, d, t_ns = 0.8, 2.5, 700
+    om, de = np.zeros(t_ns + 1), np.full(t_ns + 1, d)
+    rho0 = 0.5 * np.ones((2, 2), complex)
+    rho = lindblad.evolve(np.zeros((1, 3)), wl.C6_RB, om, de, None, t_ns, 10, rho0, 0.0, gphi)
+    t = t_ns * 1e-3
+    assert abs(rho[0, 1] - 0.5 * np.exp(-1j * d * t - gphi * t)) < 1e-13
+    assert abs(rho[1, 1] - 0.5) < 1e-14
+
+
+def test_bloch_steady_state():
+    """A driven, decaying atom relaxes to rho_11 = (Omega^2/4) / (delta^2 + Omega^2/2 +
+    gamma^2/4) (the optical Bloch equations' steady state)."""
+    om_, d, g, t_ns = 5.0, 1.5, 3.0, 12000
+    rho = lindblad.evolve(np.zeros((1, 3)), wl.C6_RB, np.full(t_ns + 1, om_),
+                          np.full(t_ns + 1, d), None, t_ns, 100, pure(np.array([1, 0], complex)), g, 0.0)
+    want = (om_ ** 2 / 4) / (d ** 2 + om_ ** 2 / 2 + g ** 2 / 4)
+    assert abs(rho[1, 1].real - want) < 1e-9
+
+
+def test_trace_hermiticity_positivity():
+    rng = np.random.default_rng(5)
+    n, t_ns = 3, 300
+    xyz = wl.random_register(n, 12.0, 4.0, rng)
+    om = wl.pwl([0, 150, 300], [0, 15, 0], t_ns)
+    de = wl.pwl([0, 300], [-10, 10], t_ns)
+    rho = lindblad.evolve(xyz, wl.C6_RB, om, de, None, t_ns, 10, pure(wl.random_state(n, rng)), 0.9, 0.4)
+    assert abs(np.trace(rho) - 1) < 1e-12
+    np.testing.assert_allclose(rho, rho.conj().T, atol=1e-14)
+    assert np.linalg.eigvalsh(rho).min() > -1e-12
+
+
+def _dense_expm():
+    f = rsv.lib()._ZN3rsv10dense_expmEiPKSt7complexIdEPS1_  # rsv::dense_expm(int, const cd*, cd*)
+    f.restype = C.c_int
+    f.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
+    return f
+
+
+@pytest.mark.parametrize("m,scale", [(1, 0.3), (2, 5.0), (7, 0.01), (20, 3.0), (40, 30.0), (63, 1.0)])
+def test_library_dense_expm_against_scipy(m, scale):
+    rng = np.random.default_rng(m)
+    a = scale * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))) / np.sqrt(m)
+    a = np.triu(a, -1)  # upper Hessenberg, as the Arnoldi process makes
+    a = np.ascontiguousarray(a)
+    out = np.empty_like(a)
+    assert _dense_expm()(m, a.ctypes.data, out.ctypes.data) == 0
+    ref = expm(a)
+    assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * max(1.0, scale)
