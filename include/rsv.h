@@ -228,6 +228,23 @@ int rsv_lindblad_evolve_device(rsv_register* reg, const rsv_pulses* pulses,
 int rsv_lindblad_occupations(rsv_ctx* ctx, int n_atoms, rsv_precision prec, const void* d_rho,
                              double* occ_out, double* trace_out, void* hip_stream);
 
+/* ------------------------------------------------------------------ gradients
+ * Derivatives of an output with respect to the pulse (Sec. IV: the emulator is
+ * differentiable): C = <psi_K| sum_i w_i n_i |psi_K> after the requested steps of eq. (6)
+ * from psi0_host (2^N complex128 values, NULL = |0...0>), and dC/dOmega_j, dC/ddelta_j for
+ * every sample j of GLOBAL pulses (per_site = 0; phi, if given, is held fixed).  Adjoint
+ * method: the forward sweep to psi_K, then backwards step by step psi_k and the adjoint
+ * lambda_k by the Lanczos exponential run backwards in time, and the derivative of each
+ * step's exponential from the Arnoldi exponential of the block operator
+ * -i [[H_k, dH/dtheta], [0, H_k]] applied to (0, psi_k); the midpoint rule of Sec. III
+ * hands half of a step's derivative to each of its two samples.  grad_omega and grad_delta
+ * have n_samples entries (zero for samples no step uses); kmax <= 63.  Cost: about
+ * (1 + 2 + 2 x 6) times the Krylov work of the forward evolution. */
+int rsv_gradient_occupations(rsv_register* reg, const rsv_pulses* pulses,
+                             const rsv_evolve_opts* opts, const double* weights,
+                             const void* psi0_host, double* value, double* grad_omega,
+                             double* grad_delta, rsv_stats* stats_out);
+
 /* ------------------------------------------------------------------ serving
  * A server evolves a stream of independent jobs (each a register, its pulses and options)
  * on one device with continuous batching: n_lanes jobs run at once, each on its own HIP

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "librsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["hpsi.hip", "packed.hip", "diag.hip", "vec.hip", "obs.hip", "tridiag.cpp", "engine.cpp", "capi.cpp", "server.cpp", "noise.cpp",
-           "lindblad.hip", "arnoldi.cpp", "dense_expm.cpp", "open_system.cpp"]
+           "lindblad.hip", "arnoldi.cpp", "dense_expm.cpp", "open_system.cpp", "gradient.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions stay off: hipcc would otherwise form them from float2 code

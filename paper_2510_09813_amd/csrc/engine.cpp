@@ -359,6 +359,7 @@ struct Lanczos {
   double yre[kMaxKrylov], yim[kMaxKrylov];
   std::vector<double> work;
   double* occ_partial = nullptr;  // fused occupation sums of an observed step's combination
+  double dir = 1.0;               // -1: exp(+i tau H), the step backwards in time
 };
 
 // Device scalar slots [first_slot, first_slot + count) through the same slots of h_scal.
@@ -555,7 +556,7 @@ int propagate(Lanczos& L, const StepCoef& c, double tau, double tol, int kmax, i
       }
     }
     L.st->krylov_max = std::max<int64_t>(L.st->krylov_max, m);
-    if (tridiag_expm(m, L.alpha, L.beta, sub, L.yre, L.yim, L.work.data()) != 0)
+    if (tridiag_expm(m, L.alpha, L.beta, L.dir * sub, L.yre, L.yim, L.work.data()) != 0)
       return fail(RSV_ENUMERIC, "tridiagonal eigensolver failed (m = %d)", m);
     CombineCoef cc;
     std::memset(&cc, 0, sizeof cc);
@@ -658,6 +659,34 @@ int evolve(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_opts* o, vo
   }
   st->norm_final = std::sqrt(L.norm2);
   st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return RSV_OK;
+}
+
+int krylov_exp(rsv_register* reg, const StepCoef& c, double tau, double dir, double tol,
+               int kmax, int max_depth, void* d_psi, hipStream_t s, rsv_stats* st) {
+  if (!reg || !d_psi) return fail(RSV_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(reg->ctx->device));
+  RSV_TRY(workspace_acquire(reg, kmax));
+  Workspace& ws = reg->ws;
+  const int n = reg->n, prec = reg->prec;
+  const size_t vb = vec_bytes(n, prec);
+  HIP_TRY(hipMemcpyAsync(ws.basis[0], d_psi, vb, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(norm2_partial(prec, n, ws.basis[0], ws.pnorm, s));
+  HIP_TRY(finalize_sum(ws.pnorm, vec_num_partials(prec, n), ws.dscal + kNormSlot, s));
+  Lanczos L;
+  L.reg = reg;
+  L.s = s;
+  L.st = st;
+  L.dir = dir < 0 ? -1.0 : 1.0;
+  std::memset(L.alpha, 0, sizeof L.alpha);
+  std::memset(L.beta, 0, sizeof L.beta);
+  std::memset(L.scale, 0, sizeof L.scale);
+  L.work.assign(tridiag_work_doubles(kMaxKrylov), 0.0);
+  RSV_TRY(fetch_scalars(L, kNormSlot, 1, &L.norm2));
+  if (L.norm2 == 0.0) return RSV_OK;  // exp(...) 0 = 0
+  RSV_TRY(propagate(L, c, tau, tol, kmax, max_depth, false));
+  HIP_TRY(hipMemcpyAsync(d_psi, ws.basis[0], vb, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return RSV_OK;
 }
 

@@ -155,6 +155,11 @@ int workspace_acquire(rsv_register* reg, int kmax);
 int evolve(rsv_register* reg, const rsv_pulses* pl, const rsv_evolve_opts* o, void* d_psi,
            hipStream_t stream, rsv_stats* st, int obs_every = 0, double* obs_out = nullptr);
 
+// d_psi <- exp(-i dir tau H_c) d_psi (dir = +1 forward, -1 backward in time) by the Lanczos
+// exponential of one step (sub-steps without convergence), with the register's workspace.
+int krylov_exp(rsv_register* reg, const StepCoef& c, double tau, double dir, double tol,
+               int kmax, int max_depth, void* d_psi, hipStream_t s, rsv_stats* st);
+
 // <n_i> and samples of a device state; d_scratch needs occupation_scratch_bytes /
 // sample_scratch_bytes; h_tmp is pinned host memory of at least 64 doubles.
 size_t occupation_scratch_bytes(int n);

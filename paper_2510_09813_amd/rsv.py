@@ -30,7 +30,7 @@ EXPORTED = [
     "rsv_occupations_device", "rsv_sample_device", "rsv_sample_device_static",
     "rsv_tridiag_expm", "rsv_evolve_device_observed", "rsv_energy_device",
     "rsv_correlations_device", "rsv_lindblad_apply", "rsv_lindblad_evolve_device",
-    "rsv_lindblad_occupations",
+    "rsv_lindblad_occupations", "rsv_gradient_occupations",
 ]
 
 
@@ -115,6 +115,8 @@ def lib():
         "rsv_lindblad_evolve_device": (i32, [vp, C.POINTER(Pulses), C.POINTER(EvolveOpts),
                                              C.POINTER(Lindblad), vp, vp, C.POINTER(Stats)]),
         "rsv_lindblad_occupations": (i32, [vp, i32, i32, vp, pd, pd, vp]),
+        "rsv_gradient_occupations": (i32, [vp, C.POINTER(Pulses), C.POINTER(EvolveOpts), pd, vp,
+                                           pd, pd, pd, C.POINTER(Stats)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -437,6 +439,29 @@ def rsv_lindblad_occupations(ctx, n_atoms: int, d_rho, precision="c128", stream=
     _check(lib().rsv_lindblad_occupations(ctx, n, prec, ptr, out.ctypes.data_as(C.POINTER(C.c_double)),
                                           C.byref(tr), _stream(stream)))
     return out, tr.value
+
+
+def rsv_gradient_occupations(reg: Register, pulses: PulseArrays, opts: EvolveOpts, weights,
+                             psi0=None):
+    """(C, dC/dOmega [n_samples], dC/ddelta [n_samples], stats) for C = sum_i w_i <n_i>
+    after the evolution, global pulses only."""
+    _check_pulses(pulses, reg.n_atoms)
+    if pulses.omega.ndim != 1:
+        raise ValueError("gradients are taken for global pulses")
+    w = _f64(weights).reshape(-1)
+    if w.size != reg.n_atoms:
+        raise ValueError(f"{w.size} weights for {reg.n_atoms} atoms")
+    buf = None if psi0 is None else _host_state(psi0, reg.n_atoms)
+    ns = pulses.omega.shape[-1]
+    go, gd = np.zeros(ns), np.zeros(ns)
+    val, st = C.c_double(), Stats()
+    pd = C.POINTER(C.c_double)
+    _check(lib().rsv_gradient_occupations(reg, C.byref(pulses.struct), C.byref(opts),
+                                          w.ctypes.data_as(pd),
+                                          buf.ctypes.data if buf is not None else None,
+                                          C.byref(val), go.ctypes.data_as(pd), gd.ctypes.data_as(pd),
+                                          C.byref(st)))
+    return val.value, go, gd, st
 
 
 def rsv_tridiag_expm(alpha, beta, tau: float):
