@@ -116,6 +116,25 @@ def test_square20_window(ctx):
     check(psi, occ, ref, "c128")
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_square20_full_run_against_oracle(ctx, prec):
+    """The 4x5 lattice sweep in full: all 400 steps from |0...0> on the plain single-job
+    path, against the Krylov oracle's final state and occupations stored by
+    tests/golden/make_square20.py (amplitudes below 1e-8 dropped: 9.2e-13 of the
+    probability, which moves the infidelity by at most about that much)."""
+    g = np.load(os.path.join(GOLDEN, "square20_final.npz"))
+    w = wl.square20()
+    psi, occ, st, res = gpu_run(ctx, w, prec)
+    rsv.rsv_result_destroy(res)
+    assert st["steps"] == w.n_steps == 400
+    ref = np.zeros(1 << w.n_atoms, dtype=np.complex128)
+    ref[g["idx"].astype(np.int64)] = g["amp"]
+    loss = check(psi, occ, ref, prec)
+    np.testing.assert_allclose(occ, g["occ"], rtol=0, atol=OCC[prec])
+    assert abs(st["norm_final"] - float(g["norm"])) <= (1e-10 if prec == "c128" else 1e-5)
+    print(f"square20 {prec}: infidelity {loss:.3e} after {w.n_steps} steps")
+
+
 @pytest.fixture(scope="module")
 def n22_window():
     """The first register size whose low pass flips bits held in neighbouring tiles (22

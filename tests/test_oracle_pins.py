@@ -352,3 +352,19 @@ def test_correlations_pins():
     np.testing.assert_allclose(observables.correlations(psi), want, atol=1e-14)
     w = np.array([0, 1, 1, 0]) / np.sqrt(2)
     np.testing.assert_allclose(observables.correlations(w), [[0.5, 0.0], [0.0, 0.5]], atol=1e-15)
+
+
+def test_square20_golden_symmetries():
+    """The stored oracle result of the 4x5 lattice sweep (tests/golden/make_square20.py):
+    global pulses on a lattice with two mirror axes give occupations invariant under both
+    reflections; the norm is conserved; the stored amplitudes reproduce the occupations."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "square20_final.npz"))
+    occ = g["occ"].reshape(4, 5)
+    np.testing.assert_allclose(occ, occ[::-1, :], atol=1e-10)
+    np.testing.assert_allclose(occ, occ[:, ::-1], atol=1e-10)
+    assert abs(float(g["norm"]) - 1.0) < 1e-12
+    psi = np.zeros(1 << 20, complex)
+    psi[g["idx"].astype(np.int64)] = g["amp"]
+    assert float(g["dropped_mass"]) < 1e-12
+    np.testing.assert_allclose(observables.occupations(psi), g["occ"], atol=2e-12)
