@@ -20,6 +20,8 @@ first (steps 0..W-1 from |0...0>), then K steps are timed (steps W..W+K-1).  Rep
              saturation, the sequential complex128 plain path's rate and latencies, and the
              infidelity and occupation error of every served result against complex128,
              and a shot-to-shot noise ensemble (512 members of the 10-atom chain),
+  lindblad   the Liouvillian on a 12-atom density matrix (GB/s) and Arnoldi steps,
+  gradient   pulse gradients at 20 atoms against the forward evolution's time,
   cpu_baseline  one time step of the CPU oracle, scaled to sim-us/s at 27 atoms.
 Every leg logs its progress to stderr at least every 20 s.
 """
@@ -349,6 +351,86 @@ def ensemble_leg(rsv, wl, ctx, members, lanes):
     return out
 
 
+def lindblad_leg(rsv, wl, ctx, n, steps):
+    """The Lindblad master equation on the random-register sweep recipe at n atoms
+    (relaxation 0.5/us, dephasing 1/us per atom, complex128, density matrix of 4^n
+    amplitudes): the Liouvillian application timed with HIP events (algorithmic bytes: the
+    density matrix read once and written once, 32 B per element), then `steps` plateau
+    steps of the Arnoldi evolution from |0...0><0...0|."""
+    import torch
+    w = wl.random27(n_atoms=n)
+    rates = (0.5, 1.0)
+    pulses = rsv.PulseArrays(w.omega, w.delta)
+    reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c128")
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    x = torch.randn(1 << (2 * n), dtype=torch.complex128, device="cuda:0", generator=g)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        rsv.rsv_lindblad_apply(reg, pulses, 200, w.dt_ns, rates, x, y)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(20):
+        rsv.rsv_lindblad_apply(reg, pulses, 200, w.dt_ns, rates, x, y)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    rho = torch.zeros_like(x)
+    rho[0] = 1
+    del x, y
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = rsv.rsv_lindblad_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, 1e-10, 40, 12, 200, steps),
+                                        rates, rho)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    occ, tr = rsv.rsv_lindblad_occupations(ctx, n, rho, "c128")
+    rsv.rsv_register_destroy(reg)
+    del rho
+    torch.cuda.empty_cache()
+    elems = 1 << (2 * n)
+    out = {"workload": f"random{n}-sweep, Lindblad (relaxation 0.5/us, dephasing 1/us)",
+           "n_atoms": n, "density_matrix_elements": elems, "precision": "complex128",
+           "liouvillian_ms": round(ms, 4),
+           "liouvillian_gbps": round(32.0 * elems / (ms * 1e-3) / 1e9, 1),
+           "steps": steps, "ms_per_step": round(wall / steps * 1e3, 2),
+           "arnoldi_iters_per_step": round(st.krylov_iters / steps, 2), "substeps": int(st.substeps),
+           "trace": tr, "occupations_sum": round(float(occ.sum()), 6)}
+    log(f"lindblad N={n}: L rho {ms:.3f} ms ({out['liouvillian_gbps']} GB/s on 32 B/element), "
+        f"{steps} steps in {wall:.2f} s")
+    return out
+
+
+def gradient_leg(rsv, wl, ctx, n, steps):
+    """Pulse gradients of sum_i <n_i> on the random-register sweep recipe at n atoms over
+    `steps` plateau steps (complex128, tol 1e-10): wall time against the forward evolution of
+    the same window."""
+    import torch
+    w = wl.random27(n_atoms=n)
+    pulses = rsv.PulseArrays(w.omega, w.delta)
+    reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c128")
+    opts = rsv.evolve_opts(w.dt_ns, 1e-10, 40, 12, 200, steps)
+    psi = torch.zeros(1 << n, dtype=torch.complex128, device="cuda:0")
+    psi[0] = 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rsv.rsv_evolve_device(reg, pulses, opts, psi)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    c, go, gd, st = rsv.rsv_gradient_occupations(reg, pulses, opts, np.ones(n))
+    t_grad = time.perf_counter() - t0
+    rsv.rsv_register_destroy(reg)
+    out = {"workload": f"random{n}-sweep, d(sum <n_i>)/d(Omega_j, delta_j)", "n_atoms": n,
+           "steps": steps, "precision": "complex128", "forward_s": round(t_fwd, 4),
+           "gradient_s": round(t_grad, 4), "ratio": round(t_grad / t_fwd, 2),
+           "value": c, "grad_omega_norm": float(np.linalg.norm(go)),
+           "grad_delta_norm": float(np.linalg.norm(gd)), "krylov_iters": int(st.krylov_iters)}
+    log(f"gradient N={n}: {steps} steps forward {t_fwd:.3f} s, gradient {t_grad:.3f} s")
+    return out
+
+
 def capacity_leg(rsv, wl, ctx, steps):
     """The 5x6 triangular quench at 30 atoms in complex64 (FP64 Lanczos scalars and host
     tridiagonal exponential, kmax 20, dt = 5 ns): the first `steps` steps from |0...0>."""
@@ -438,6 +520,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--n30-steps", type=int, default=3,
                     help="steps of the 30-atom complex64 leg (0: skip it)")
+    ap.add_argument("--no-next", dest="next_rows", action="store_false",
+                    help="skip the Lindblad and gradient legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state vector of one job lives on one MI355X; "
@@ -517,6 +601,9 @@ def main():
     torch.cuda.empty_cache()
     if args.n30_steps > 0:
         out["n30_c64"] = capacity_leg(rsv, wl, ctx, args.n30_steps)
+    if args.next_rows:
+        out["lindblad"] = lindblad_leg(rsv, wl, ctx, 12, 3)
+        out["gradient"] = gradient_leg(rsv, wl, ctx, 20, 10)
     if args.serve_jobs > 0:
         out["serving"] = serving_leg(rsv, wl, ctx, args.serve_jobs, args.lanes)
         out["serving"]["small_jobs"] = small_job_leg(rsv, wl, ctx, 160, args.lanes)

@@ -213,7 +213,9 @@ typedef struct {
   double dephasing_rate;
 } rsv_lindblad;
 
-/* d_out = L_k d_in for step `step` (test and benchmark hook); returns after the stream finished. */
+/* d_out = L_k d_in for step `step` (test and benchmark hook).  The kernel is enqueued on
+ * hip_stream and the call returns without waiting (the register's interaction energies are
+ * built on its first Lindblad call and kept). */
 int rsv_lindblad_apply(rsv_register* reg, const rsv_pulses* pulses, int64_t step, int dt_ns,
                        const rsv_lindblad* rates, const void* d_in, void* d_out, void* hip_stream);
 /* rho <- exp(dt L_{k}) rho for the requested steps (opts as for rsv_evolve_device; reorth is
@@ -282,6 +284,10 @@ typedef struct {
   uint64_t seed;
   int return_state;      /* 1: the completion carries the final state as complex128 */
   uint64_t tag;          /* caller's label, returned unchanged */
+  int verify_fp64;       /* RSV_C64 jobs: 1 = also evolve the job in complex128 (tol at most
+                            1e-10) and report the complex64 result's infidelity and largest
+                            occupation error against it; the job then runs on the plain path
+                            and occupies both workspaces */
 } rsv_job_desc;
 
 typedef struct {
@@ -294,6 +300,11 @@ typedef struct {
   uint64_t* samples;   /* [n_shots] or NULL */
   void* state;         /* [2^N] complex128 or NULL */
   char error[160];
+  /* verify_fp64 jobs: 1 - |<psi_128|psi>|^2 / (|psi_128|^2 |psi|^2) (FP64, so resolved to
+   * about 1e-16) and max_i |<n_i> - <n_i>_128| against the complex128 evolution of the same
+   * job; -1 otherwise */
+  double infidelity_fp64;
+  double max_occ_err_fp64;
 } rsv_completion;
 
 /* Shot-to-shot parameter noise (Sec. III.A: open-system effects by varying the Hamiltonian's

@@ -311,6 +311,7 @@ void register_destroy(rsv_register* reg, hipStream_t stream) {
   (void)hipStreamSynchronize(stream);
   workspace_release(reg);
   if (reg->d_hbuf) reg->alloc->release(reg->d_hbuf, vec_bytes(reg->n, reg->prec));
+  if (reg->d_efull) reg->alloc->release(reg->d_efull, (size_t(1) << reg->n) * sizeof(double));
   if (reg->d_ub) reg->alloc->release(reg->d_ub, reg->bytes);
   if (reg->own_h_scal && reg->h_scal) (void)hipHostFree(reg->h_scal);
   if (reg->have_ev)

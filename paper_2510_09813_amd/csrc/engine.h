@@ -119,6 +119,7 @@ struct rsv_register {
   double* d_ub = nullptr;
   double* d_dtab = nullptr;  // interaction-diagonal tables of the H psi low pass
   void* d_hbuf = nullptr;  // high-bit partial of rsv_apply_hamiltonian
+  double* d_efull = nullptr;  // the 2^N interaction energies (FP64) of the Lindblad path
   size_t bytes = 0;
   rsv::Workspace ws;
   double* h_scal = nullptr;  // pinned host scalars of the per-iteration exchange

@@ -70,6 +70,22 @@ struct Block {
 
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
+// The register's 2^N interaction energies in FP64, built on first use and kept.
+int energies(rsv_register* reg, hipStream_t s, const double** out) {
+  if (!reg->d_efull) {
+    void* p = nullptr;
+    RSV_TRY(reg->alloc->alloc((size_t(1) << reg->n) * sizeof(double), &p));
+    const hipError_t e = diag_build(kC128, reg->n, reg->d_ub, p, s);
+    if (e != hipSuccess) {
+      reg->alloc->release(p, (size_t(1) << reg->n) * sizeof(double));
+      return fail(RSV_EDEVICE, "interaction energies: %s", hipGetErrorString(e));
+    }
+    reg->d_efull = (double*)p;
+  }
+  *out = reg->d_efull;
+  return RSV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -85,12 +101,10 @@ int rsv_lindblad_apply(rsv_register* reg, const rsv_pulses* pl, int64_t step, in
   if (step < 0 || step >= K) return fail(RSV_EINVAL, "step outside the pulse");
   HIP_TRY(hipSetDevice(reg->ctx->device));
   hipStream_t s = as_stream(stream);
-  Block e(reg->alloc, s);
-  RSV_TRY(e.get(up256((size_t(1) << reg->n) * sizeof(double))));
-  HIP_TRY(diag_build(kC128, reg->n, reg->d_ub, e.p, s));
+  const double* e = nullptr;
+  RSV_TRY(energies(reg, s, &e));
   const LindbladCoef lc = lindblad_coef(step_coef(pl, reg->n, step, dt_ns), rates);
-  HIP_TRY(liouvillian_apply(reg->prec, lc, (const double*)e.p, d_in, d_out, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(liouvillian_apply(reg->prec, lc, e, d_in, d_out, s));
   return RSV_OK;
 }
 
@@ -108,13 +122,12 @@ int rsv_lindblad_evolve_device(rsv_register* reg, const rsv_pulses* pl, const rs
   HIP_TRY(hipSetDevice(reg->ctx->device));
   hipStream_t s = as_stream(stream);
   const int n = reg->n, prec = reg->prec;
-  const size_t eb = up256((size_t(1) << n) * sizeof(double));
+  const double* e = nullptr;
+  RSV_TRY(energies(reg, s, &e));
   Block blk(reg->alloc, s);
-  RSV_TRY(blk.get(eb + arnoldi_device_bytes(prec, 2 * n, o->kmax)));
-  double* e = (double*)blk.p;
-  HIP_TRY(diag_build(kC128, n, reg->d_ub, e, s));
+  RSV_TRY(blk.get(arnoldi_device_bytes(prec, 2 * n, o->kmax)));
   ArnoldiSpace sp;
-  arnoldi_carve((char*)blk.p + eb, reg->h_scal, prec, 2 * n, o->kmax, &sp);
+  arnoldi_carve(blk.p, reg->h_scal, prec, 2 * n, o->kmax, &sp);
   rsv_stats st{};
   const double tau = o->dt_ns * 1e-3;
   for (int64_t k = first; k < first + count; ++k) {

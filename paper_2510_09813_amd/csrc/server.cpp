@@ -70,7 +70,7 @@ constexpr int kPackOutDoubles = 64;
 
 struct Job {
   uint64_t id = 0, tag = 0;
-  int n = 0, prec = 0, shots = 0, return_state = 0;
+  int n = 0, prec = 0, shots = 0, return_state = 0, verify = 0;
   int64_t first_step = 0, n_steps = 0;
   bool packed = false, taken = false;
   size_t up = 0, down = 0, work = 0;  // packed footprint: uploaded, downloaded, device-only
@@ -114,6 +114,66 @@ void fill_error(rsv_completion& c, int status) {
     std::strncpy(c.error, last_error(), sizeof c.error - 1);
     c.error[sizeof c.error - 1] = 0;
   }
+}
+
+// The precision report of a complex64 job: the same job evolved in complex128 (tolerance at
+// most 1e-10) in the rest of the job's block, then 1 - |<a|b>|^2 / (|a|^2 |b|^2) and the
+// largest occupation difference, all sums FP64 on the device.
+int verify_fp64(rsv_server* srv, Job* job, const void* d_psi64,
+                BumpAllocator& bump, hipStream_t stream, double* h_pinned, rsv_completion& c) {
+  const int n = job->n;
+  rsv_register* reg = nullptr;
+  RSV_TRY(register_create(srv->ctx, &bump, n, job->xyz.data(), job->c6, kC128, stream, h_pinned,
+                          &reg));
+  struct Guard {
+    rsv_register* r;
+    hipStream_t s;
+    ~Guard() { register_destroy(r, s); }
+  } guard{reg, stream};
+  RSV_TRY(workspace_acquire(reg, job->opts.kmax));
+  void *d_psi = nullptr, *occ_scratch = nullptr;
+  RSV_TRY(bump.alloc(vec_bytes(n, kC128), &d_psi));
+  RSV_TRY(bump.alloc(occupation_scratch_bytes(n), &occ_scratch));
+  const size_t b128 = (size_t(1) << n) * 16;
+  if (!job->psi0.empty()) {
+    HIP_TRY(hipMemcpyAsync(d_psi, job->psi0.data(), b128, hipMemcpyHostToDevice, stream));
+  } else {
+    HIP_TRY(hipMemsetAsync(d_psi, 0, b128, stream));
+    h_pinned[0] = 1.0;
+    h_pinned[1] = 0.0;
+    HIP_TRY(hipMemcpyAsync(d_psi, h_pinned, 16, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
+  rsv_evolve_opts o = job->opts;
+  o.tol = std::min(o.tol, 1e-10);
+  rsv_stats st{};
+  RSV_TRY(evolve(reg, &job->pulses, &o, d_psi, stream, &st));
+  std::vector<double> occ(n);
+  RSV_TRY(occupations_with(n, kC128, d_psi, occ_scratch, h_pinned, occ.data(), stream));
+  double err = 0.0;
+  for (int i = 0; i < n; ++i) err = std::max(err, std::abs(occ[i] - c.occupations[i]));
+  // the complex64 state widened into the complex128 register's workspace vector z, then
+  // <a, b>, |a|^2, |b|^2 with the two-stage FP64 sums
+  void* wide = reg->ws.z;
+  HIP_TRY(convert_to_c128(kC64, n, d_psi64, wide, stream));
+  double* part = reg->ws.pnorm;
+  double* res = reg->ws.dscal;
+  const int64_t nw = vec_num_partials(kC128, n);
+  DotGroup d{};
+  d.g = 1;
+  d.x[0] = d_psi;
+  HIP_TRY(multi_dot(kC128, n, d, wide, part, stream));
+  HIP_TRY(finalize_rows(part, nw, 2, res, stream));
+  HIP_TRY(norm2_partial(kC128, n, d_psi, part, stream));
+  HIP_TRY(finalize_sum(part, nw, res + 2, stream));
+  HIP_TRY(norm2_partial(kC128, n, wide, part, stream));
+  HIP_TRY(finalize_sum(part, nw, res + 3, stream));
+  HIP_TRY(hipMemcpyAsync(h_pinned, res, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const double ab2 = h_pinned[0] * h_pinned[0] + h_pinned[1] * h_pinned[1];
+  c.infidelity_fp64 = std::max(0.0, 1.0 - ab2 / (h_pinned[2] * h_pinned[3]));
+  c.max_occ_err_fp64 = err;
+  return RSV_OK;
 }
 
 // Runs one admitted job on `stream`; the job's memory is job->block.
@@ -172,6 +232,7 @@ int run_job(rsv_server* srv, Job* job, hipStream_t stream, double* h_pinned, rsv
     HIP_TRY(hipMemcpyAsync(c.state, src, b128, hipMemcpyDeviceToHost, stream));
   }
   HIP_TRY(hipStreamSynchronize(stream));
+  if (job->verify) RSV_TRY(verify_fp64(srv, job, d_psi, bump, stream, h_pinned, c));
   return RSV_OK;
 }
 
@@ -408,6 +469,7 @@ int run_batch(rsv_server* srv, Work& w, LaneBuffers& lb, std::vector<rsv_complet
     Job* j = w.jobs[i];
     rsv_completion c;
     std::memset(&c, 0, sizeof c);
+    c.infidelity_fp64 = c.max_occ_err_fp64 = -1.0;
     c.job_id = j->id;
     c.tag = j->tag;
     c.n_atoms = j->n;
@@ -480,6 +542,7 @@ void lane_main(rsv_server* srv) {
         for (Job* j : w.jobs) {
           rsv_completion c;
           std::memset(&c, 0, sizeof c);
+          c.infidelity_fp64 = c.max_occ_err_fp64 = -1.0;
           c.job_id = j->id;
           c.tag = j->tag;
           c.n_atoms = j->n;
@@ -494,6 +557,7 @@ void lane_main(rsv_server* srv) {
       Job* job = w.jobs[0];
       rsv_completion c;
       std::memset(&c, 0, sizeof c);
+      c.infidelity_fp64 = c.max_occ_err_fp64 = -1.0;
       c.job_id = job->id;
       c.tag = job->tag;
       c.n_atoms = job->n;
@@ -557,6 +621,7 @@ int make_job(rsv_server* srv, const rsv_job_desc* jd, std::unique_ptr<Job>* out)
   j->shots = jd->n_shots;
   j->seed = jd->seed;
   j->return_state = jd->return_state;
+  j->verify = jd->verify_fp64 && jd->prec == kC64;
   j->c6 = jd->c6;
   j->xyz.assign(jd->xyz_um, jd->xyz_um + 3 * n);
   const size_t cnt = (size_t)jd->pulses.n_samples * (jd->pulses.per_site ? (size_t)n : 1);
@@ -575,7 +640,8 @@ int make_job(rsv_server* srv, const rsv_job_desc* jd, std::unique_ptr<Job>* out)
   j->first_step = first;
   j->n_steps = count;
   // the packed kernel runs the three-term recurrence only
-  j->packed = !jd->opts.reorth && n <= std::min(srv->opts.pack_max_atoms, packed_max_atoms(jd->prec));
+  j->packed = !jd->opts.reorth && !j->verify &&
+              n <= std::min(srv->opts.pack_max_atoms, packed_max_atoms(jd->prec));
   if (j->packed) {
     packed_sizes(*j);
     // too large for one staging buffer: the plain path takes it
@@ -583,6 +649,7 @@ int make_job(rsv_server* srv, const rsv_job_desc* jd, std::unique_ptr<Job>* out)
   }
   j->bytes = j->packed ? batch_bytes(1, j->up, j->down, j->work)
                        : job_bytes(n, jd->opts.kmax, jd->prec, jd->n_shots);
+  if (j->verify) j->bytes += job_bytes(n, jd->opts.kmax, kC128, 0);  // the reference run
   if (j->bytes > srv->arena.capacity())
     return fail(RSV_ENOMEM, "job needs %zu bytes, the arena holds %zu", j->bytes,
                 srv->arena.capacity());
@@ -742,6 +809,7 @@ int rsv_server_cancel(rsv_server* srv, uint64_t job_id) {
     }
     rsv_completion c;
     std::memset(&c, 0, sizeof c);
+    c.infidelity_fp64 = c.max_occ_err_fp64 = -1.0;
     c.job_id = victim->id;
     c.tag = victim->tag;
     c.n_atoms = victim->n;

@@ -486,7 +486,7 @@ class JobDesc(C.Structure):
     _fields_ = [("n_atoms", C.c_int), ("xyz_um", C.POINTER(C.c_double)), ("c6", C.c_double),
                 ("prec", C.c_int), ("pulses", Pulses), ("opts", EvolveOpts),
                 ("psi0_host", C.c_void_p), ("n_shots", C.c_int), ("seed", C.c_uint64),
-                ("return_state", C.c_int), ("tag", C.c_uint64)]
+                ("return_state", C.c_int), ("tag", C.c_uint64), ("verify_fp64", C.c_int)]
 
 
 class Completion(C.Structure):
@@ -494,7 +494,8 @@ class Completion(C.Structure):
                 ("n_atoms", C.c_int), ("n_shots", C.c_int), ("t_submit", C.c_double),
                 ("t_start", C.c_double), ("t_end", C.c_double), ("stats", Stats),
                 ("occupations", C.POINTER(C.c_double)), ("samples", C.POINTER(C.c_uint64)),
-                ("state", C.c_void_p), ("error", C.c_char * 160)]
+                ("state", C.c_void_p), ("error", C.c_char * 160),
+                ("infidelity_fp64", C.c_double), ("max_occ_err_fp64", C.c_double)]
 
 
 def _server_sigs(L):
@@ -555,13 +556,14 @@ def rsv_server_job_bytes(n_atoms: int, kmax: int, precision="c64", n_shots: int 
 
 def rsv_server_submit(srv, xyz, c6, pulses: PulseArrays, opts: EvolveOpts, precision="c64",
                       psi0=None, n_shots: int = 0, seed: int = 0, return_state: bool = False,
-                      tag: int = 0) -> int:
+                      tag: int = 0, verify_fp64: bool = False) -> int:
     xyz = _f64(xyz).reshape(-1, 3)
     _check_pulses(pulses, xyz.shape[0])
     buf = None if psi0 is None else _host_state(psi0, xyz.shape[0])
     jd = JobDesc(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), float(c6),
                  PRECISIONS.get(precision, precision), pulses.struct, opts,
-                 buf.ctypes.data if buf is not None else None, n_shots, seed, int(return_state), tag)
+                 buf.ctypes.data if buf is not None else None, n_shots, seed, int(return_state), tag,
+                 int(verify_fp64))
     jid = C.c_uint64()
     _check(_slib().rsv_server_submit(srv, C.byref(jd), C.byref(jid)))
     return int(jid.value)
@@ -610,6 +612,7 @@ def rsv_server_poll(srv, max_n: int = 64, timeout_ms: int = -1):
         d = {"job_id": int(c.job_id), "tag": int(c.tag), "status": int(c.status),
              "n_atoms": int(c.n_atoms), "t_submit": c.t_submit, "t_start": c.t_start,
              "t_end": c.t_end, "stats": c.stats.as_dict(), "error": c.error.decode(errors="replace"),
+             "infidelity_fp64": c.infidelity_fp64, "max_occ_err_fp64": c.max_occ_err_fp64,
              "occupations": None, "samples": None, "state": None}
         if c.occupations:
             d["occupations"] = np.ctypeslib.as_array(c.occupations, (c.n_atoms,)).copy()

@@ -276,3 +276,40 @@ def test_packed_options_rejected(ctx):
         with pytest.raises(rsv.RsvError) as e:
             rsv.rsv_server_create(ctx, n_lanes=1, arena_bytes=1 << 20, **kw)
         assert e.value.code == rsv.RSV_EINVAL
+
+
+def test_per_result_precision_report(ctx):
+    """complex64 jobs submitted with verify_fp64 carry their infidelity and largest
+    occupation error against the complex128 evolution of the same job; the figures agree with
+    an independent complex128 run of the plain path, and stay within the 1e-6 bar."""
+    rng = np.random.default_rng(31)
+    jobs = [wl.serving_job(rng, n_min=n, n_max=n) for n in (9, 14, 17)]
+    for w in jobs:
+        w.t_ns, w.omega, w.delta = 300, w.omega[:301], w.delta[:301]
+    srv = rsv.rsv_server_create(ctx, n_lanes=2, arena_bytes=2 << 30, pack_max_atoms=13)
+    try:
+        for i, w in enumerate(jobs):
+            rsv.rsv_server_submit(srv, w.xyz, w.c6, rsv.PulseArrays(w.omega, w.delta),
+                                  rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12), "c64",
+                                  return_state=True, tag=i, verify_fp64=True)
+        rsv.rsv_server_submit(srv, jobs[0].xyz, jobs[0].c6,
+                              rsv.PulseArrays(jobs[0].omega, jobs[0].delta),
+                              rsv.evolve_opts(10, 1e-7, 30, 12), "c64", tag=99)
+        done = {c["tag"]: c for c in drain(srv, len(jobs) + 1)}
+    finally:
+        rsv.rsv_server_destroy(srv)
+    assert done[99]["infidelity_fp64"] == -1.0 and done[99]["max_occ_err_fp64"] == -1.0
+    for i, w in enumerate(jobs):
+        c = done[i]
+        assert c["status"] == rsv.RSV_OK, c["error"]
+        reg = rsv.rsv_register_create(ctx, w.xyz, w.c6, "c128")
+        res = rsv.rsv_evolve(reg, rsv.PulseArrays(w.omega, w.delta),
+                             rsv.evolve_opts(w.dt_ns, 1e-10, w.kmax, 12))
+        ref = rsv.rsv_result_state(res, w.n_atoms)
+        occ = rsv.rsv_result_occupations(res, w.n_atoms)
+        rsv.rsv_result_destroy(res)
+        rsv.rsv_register_destroy(reg)
+        loss = observables.fidelity_loss(ref, c["state"])
+        assert 0.0 <= c["infidelity_fp64"] <= 1e-6
+        assert abs(c["infidelity_fp64"] - loss) <= 1e-13, (c["infidelity_fp64"], loss)
+        assert abs(c["max_occ_err_fp64"] - np.abs(occ - c["occupations"]).max()) <= 1e-12
