@@ -219,6 +219,7 @@ def serving_leg(rsv, wl, ctx, n_jobs, lanes):
     arrivals = arrivals - arrivals[0]
     steady, span = serve_jobs(rsv, ctx, jobs, lanes, arena, arrivals)
     lat = [c["t_end"] - c["t_submit"] for c in steady]
+    wait = [c["t_start"] - c["t_submit"] for c in steady]
     seq_lat, t_free = [], 0.0
     for a, s_ in zip(arrivals, service):
         t_free = max(t_free, a) + s_
@@ -240,6 +241,8 @@ def serving_leg(rsv, wl, ctx, n_jobs, lanes):
         "arrival_rate_per_s": round(rate, 3),
         "served_solves_per_s": round(len(jobs) / span, 3),
         "served_p50_s": round(percentile(lat, 50), 4), "served_p99_s": round(percentile(lat, 99), 4),
+        "served_queue_wait_p50_s": round(percentile(wait, 50), 4),
+        "served_queue_wait_p99_s": round(percentile(wait, 99), 4),
         "sequential_c128_service_solves_per_s": round(mu_seq, 3),
         "sequential_p50_s": round(percentile(seq_lat, 50), 4),
         "sequential_p99_s": round(percentile(seq_lat, 99), 4),
