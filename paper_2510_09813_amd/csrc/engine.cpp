@@ -91,10 +91,8 @@ int ArenaAllocator::init(size_t bytes) {
     base_ = nullptr;
     return fail(RSV_ENOMEM, "arena hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
   }
-  size_ = bytes;
-  free_.clear();
-  free_[0] = bytes;
-  used_ = 0;
+  std::lock_guard<std::mutex> lk(mu_);
+  ff_.reset(bytes);
   return RSV_OK;
 }
 
@@ -102,43 +100,24 @@ int ArenaAllocator::alloc(size_t bytes, void** p) {
   *p = nullptr;
   bytes = round_up(bytes ? bytes : 1);
   std::lock_guard<std::mutex> lk(mu_);
-  for (auto it = free_.begin(); it != free_.end(); ++it) {
-    if (it->second < bytes) continue;
-    const size_t off = it->first, len = it->second;
-    free_.erase(it);
-    if (len > bytes) free_[off + bytes] = len - bytes;
-    used_ += bytes;
-    *p = base_ + off;
-    return RSV_OK;
-  }
-  return fail(RSV_ENOMEM, "arena has no free block of %zu bytes (%zu of %zu in use)", bytes, used_,
-              size_);
+  size_t off = 0;
+  if (!ff_.take(bytes, &off))
+    return fail(RSV_ENOMEM, "arena has no free block of %zu bytes (%zu of %zu in use)", bytes,
+                ff_.used(), ff_.size());
+  *p = base_ + off;
+  return RSV_OK;
 }
 
 void ArenaAllocator::release(void* p, size_t bytes) {
   if (!p) return;
   bytes = round_up(bytes ? bytes : 1);
   std::lock_guard<std::mutex> lk(mu_);
-  size_t off = (size_t)((char*)p - base_), len = bytes;
-  used_ -= bytes;
-  auto next = free_.lower_bound(off);
-  if (next != free_.end() && off + len == next->first) {  // merge with the following gap
-    len += next->second;
-    next = free_.erase(next);
-  }
-  if (next != free_.begin()) {  // merge with the preceding gap
-    auto prev = std::prev(next);
-    if (prev->first + prev->second == off) {
-      prev->second += len;
-      return;
-    }
-  }
-  free_[off] = len;
+  ff_.give((size_t)((char*)p - base_), bytes);
 }
 
 size_t ArenaAllocator::in_use() const {
   std::lock_guard<std::mutex> lk(mu_);
-  return used_;
+  return ff_.used();
 }
 
 size_t vec_bytes(int n, int prec) { return (size_t(1) << n) * amp_bytes(prec); }

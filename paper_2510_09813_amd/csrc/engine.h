@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "first_fit.h"
 #include "rsv.h"
 #include "rsv_internal.h"
 
@@ -65,12 +66,11 @@ class ArenaAllocator : public Allocator {
   int alloc(size_t bytes, void** p) override;  // RSV_ENOMEM when no gap is large enough
   void release(void* p, size_t bytes) override;
   size_t in_use() const override;
-  size_t capacity() const { return size_; }
+  size_t capacity() const { return ff_.size(); }
 
  private:
   char* base_ = nullptr;
-  size_t size_ = 0, used_ = 0;
-  std::map<size_t, size_t> free_;  // offset -> length
+  FirstFit ff_;
   mutable std::mutex mu_;
 };
 
