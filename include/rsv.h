@@ -263,7 +263,8 @@ int rsv_gradient_occupations(rsv_register* reg, const rsv_pulses* pulses,
  * its job's whole evolution with the state on chip.  The method is that of Sec. III.A with
  * the small exponential evaluated on the device (a Chebyshev expansion), so a packed result
  * agrees with the plain path to the tolerance, not bit for bit; it is still independent of
- * the batch it ran in. */
+ * the batch it ran in.  With packing on, the server runs one lane more than n_lanes that
+ * takes only packed batches, so small jobs do not wait for lanes held by long jobs. */
 typedef struct {
   int n_lanes;        /* concurrent jobs, 1..16 */
   size_t arena_bytes; /* device memory reserved for jobs; 0 = three quarters of free memory */

@@ -11,7 +11,9 @@
 // Small jobs are packed: a lane takes every queued small job of one precision (up to the
 // batch limit and its pinned staging size) as one arena block, uploads all their inputs
 // with one copy, builds each diagonal, runs them in one launch of the packed kernel (one
-// workgroup per job) and downloads all outputs with one copy.
+// workgroup per job) and downloads all outputs with one copy.  With packing on, one lane
+// beyond n_lanes takes only packed batches, so small jobs never queue behind long jobs that
+// hold every regular lane.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -309,13 +311,14 @@ bool take_batch(rsv_server* srv, size_t first, Work& w) {
 }
 
 // First queued work (arrival order) whose memory fits: a plain job, or a packed batch led
-// by the first packed job that fits.
-bool take_work(rsv_server* srv, std::unique_lock<std::mutex>& lk, Work& w) {
+// by the first packed job that fits (packed_only: the small-job lane takes only those).
+bool take_work(rsv_server* srv, std::unique_lock<std::mutex>& lk, Work& w, bool packed_only) {
   for (;;) {
     if (srv->stop) return false;
     for (size_t q = 0; q < srv->queue.size(); ++q) {
       Job* j = srv->queue[q];
       bool got = false;
+      if (packed_only && !j->packed) continue;
       if (j->packed) {
         got = take_batch(srv, q, w);
       } else {
@@ -515,7 +518,7 @@ int run_batch(rsv_server* srv, Work& w, LaneBuffers& lb, std::vector<rsv_complet
   return RSV_OK;
 }
 
-void lane_main(rsv_server* srv) {
+void lane_main(rsv_server* srv, bool packed_only) {
   (void)hipSetDevice(srv->ctx->device);
   LaneBuffers lb;
   bool ok = hipStreamCreateWithFlags(&lb.stream, hipStreamNonBlocking) == hipSuccess &&
@@ -528,7 +531,7 @@ void lane_main(rsv_server* srv) {
     Work w;
     {
       std::unique_lock<std::mutex> lk(srv->mu);
-      if (!take_work(srv, lk, w)) break;
+      if (!take_work(srv, lk, w, packed_only)) break;
     }
     std::vector<rsv_completion> comps;
     const double t_start = srv->now();
@@ -709,7 +712,10 @@ int rsv_server_create(rsv_ctx* ctx, const rsv_server_opts* opts, rsv_server** ou
   s->opts = *opts;
   RSV_TRY(s->arena.init(bytes));
   s->t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < opts->n_lanes; ++i) s->lanes.emplace_back(lane_main, s.get());
+  for (int i = 0; i < opts->n_lanes; ++i) s->lanes.emplace_back(lane_main, s.get(), false);
+  // with packing, one more lane runs only packed batches: a small job then never waits for a
+  // lane held by a long plain job
+  if (opts->pack_max_atoms > 0) s->lanes.emplace_back(lane_main, s.get(), true);
   *out = s.release();
   return RSV_OK;
 }
