@@ -154,7 +154,7 @@ def occupations_of(psi):
     return np.array([np.take(t, 1, axis=i).sum() for i in range(n)]) / p.sum()
 
 
-def serve_jobs(rsv, ctx, jobs, lanes, arena, arrivals=None):
+def serve_jobs(rsv, ctx, jobs, lanes, arena, arrivals=None, return_state=True):
     """Runs jobs through one server (complex64, jobs of <= 13 atoms packed); arrivals[i] is
     job i's submission time in seconds from the start (None: all at once).  Returns the
     completions and the wall span from the first submission to the last completion."""
@@ -170,7 +170,7 @@ def serve_jobs(rsv, ctx, jobs, lanes, arena, arrivals=None):
                     prog(f"{len(done)} of {len(jobs)} done, {i} submitted")
             rsv.rsv_server_submit(srv, w.xyz, w.c6, pulses[i],
                                   rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12), "c64",
-                                  return_state=True, tag=i)
+                                  return_state=return_state, tag=i)
         while len(done) < len(jobs):
             done += rsv.rsv_server_poll(srv, 64, 1000)
             prog(f"{len(done)} of {len(jobs)} done")
@@ -256,6 +256,33 @@ def serving_leg(rsv, wl, ctx, n_jobs, lanes):
         f"{out['served_p50_s']} s, p99 {out['served_p99_s']} s; max infidelity "
         f"{out['max_infidelity_vs_c128']:.2e}")
     return out
+
+
+def serving_full(rsv, wl, ctx, n_jobs, rate, lanes):
+    """The whole serving stream (n_jobs of the N ~ U{12..24} recipe, complex64, jobs of <= 13
+    atoms packed) at Poisson arrivals of the given rate: served solves/s, latency and queue
+    wait percentiles, overall and by register size.  No complex128 reference here: the
+    precision of served results is measured on the stream's prefix by the default run."""
+    jobs = wl.serving_stream(n_jobs, seed=0)
+    arrivals = wl.poisson_arrivals(len(jobs), rate, seed=1)
+    arrivals = arrivals - arrivals[0]
+    arena = 2 * sum(sorted(rsv.rsv_server_job_bytes(w.n_atoms, w.kmax, "c64", 0) for w in jobs)[-lanes:])
+    done, span = serve_jobs(rsv, ctx, jobs, lanes, arena, arrivals, return_state=False)
+    lat = [c["t_end"] - c["t_submit"] for c in done]
+    wait = [c["t_start"] - c["t_submit"] for c in done]
+    by_n = {}
+    for w, c in zip(jobs, done):
+        by_n.setdefault(int(w.n_atoms), []).append(c["t_end"] - c["t_submit"])
+    return {
+        "jobs": len(jobs), "lanes": lanes, "arrival_rate_per_s": rate,
+        "precision": "c64 state, FP64 reductions, tol 1e-7; jobs <= 13 atoms packed",
+        "served_solves_per_s": round(len(jobs) / span, 3), "span_s": round(span, 2),
+        "served_p50_s": round(percentile(lat, 50), 4), "served_p99_s": round(percentile(lat, 99), 4),
+        "queue_wait_p50_s": round(percentile(wait, 50), 4),
+        "queue_wait_p99_s": round(percentile(wait, 99), 4),
+        "p50_by_n_atoms": {n: round(percentile(v, 50), 4) for n, v in sorted(by_n.items())},
+        "sim_us_served": round(sum(w.t_ns for w in jobs) * 1e-3, 1),
+    }
 
 
 def small_job_leg(rsv, wl, ctx, n_jobs, lanes):
@@ -525,6 +552,9 @@ def main():
                     help="steps of the 30-atom complex64 leg (0: skip it)")
     ap.add_argument("--no-next", dest="next_rows", action="store_false",
                     help="skip the Lindblad and gradient legs")
+    ap.add_argument("--serve-full", type=int, default=0,
+                    help="only serve this many jobs of the stream at --serve-rate and report")
+    ap.add_argument("--serve-rate", type=float, default=2.4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state vector of one job lives on one MI355X; "
@@ -535,6 +565,12 @@ def main():
     from paper_2510_09813_amd import rsv
     from paper_2510_09813_amd import workloads as wl
     torch.cuda.set_device(0)
+    if args.serve_full > 0:
+        ctx = rsv.rsv_ctx_create(0)
+        out = serving_full(rsv, wl, ctx, args.serve_full, args.serve_rate, args.lanes)
+        rsv.rsv_ctx_destroy(ctx)
+        print(json.dumps(out), flush=True)
+        return
     w = wl.random27()
     n = w.n_atoms
     K, W = args.steps, args.warmup
