@@ -42,6 +42,17 @@ def liouvillian(h: np.ndarray, ops) -> np.ndarray:
     return lv
 
 
+def apply_liouvillian(rho, h, ops) -> np.ndarray:
+    """d rho/dt from its definition with matrix products (no superoperator): for checking
+    the operator at sizes whose 4^N x 4^N matrix would not fit."""
+    rho = np.asarray(rho, dtype=np.complex128)
+    out = -1j * (h @ rho - rho @ h)
+    for op in ops:
+        ld = op.conj().T @ op
+        out += op @ rho @ op.conj().T - 0.5 * (ld @ rho + rho @ ld)
+    return out
+
+
 def evolve(xyz, c6, omega, delta, phi, t_ns: int, dt_ns: int, rho0, gamma_r: float,
            gamma_phi: float, steps=None, first_step: int = 0) -> np.ndarray:
     """rho after steps first_step .. first_step + steps - 1 of rho_{k+1} = exp(dt L_k) rho_k."""

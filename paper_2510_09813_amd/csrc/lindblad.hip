@@ -14,9 +14,10 @@
 //              + gamma_r sum_{p: r_p = c_p = 0} rho_{r|p, c|p}
 //
 // where D_x = E_x - sum_p delta_p x_p is H's diagonal (E_x the interaction energy of pattern
-// x), h(1) = <1|h_p|0> = Omega_p/2 e^{-i phi_p} and h(0) = <0|h_p|1>.  One thread per element
-// gathers its 3n + 1 inputs through the cache (the 4^n vector is at most 4 GiB: n <= 14), all
-// arithmetic in FP64, stored in the storage precision.
+// x), h(1) = <1|h_p|0> = Omega_p/2 e^{-i phi_p} and h(0) = <0|h_p|1>.  Every element needs
+// 3n + 1 inputs; arithmetic is FP64, results are stored in the storage precision, and the
+// 4^n vector is at most 4 GiB (n <= 14).  Below 6 atoms one thread per element gathers its
+// inputs through the cache; from 6 atoms on, tiles of 4096 elements go through LDS.
 #include "device_common.h"
 #include "lindblad.h"
 
@@ -73,6 +74,64 @@ __global__ __launch_bounds__(kBlock) void liouvillian_kernel(const LindbladCoef 
   }
 }
 
+// The same operator on tiles of 2^12 consecutive elements (n >= 6): the tile sits in LDS, so
+// the flips of the 12 low index bits (the column bits, and for n < 12 the low row bits) read
+// LDS; the flips of higher bits read the neighbouring tiles from global memory (one coalesced
+// read per bit), and the relaxation's double flips read LDS when both bits lie in the tile.
+constexpr int kTileBits = 12, kTileThreads = 512, kTilePer = (1 << kTileBits) / kTileThreads;
+
+template <class R>
+__global__ __launch_bounds__(kTileThreads) void liouvillian_tile_kernel(
+    const LindbladCoef c, const double* __restrict__ e, const Cx<R>* __restrict__ x,
+    Cx<R>* __restrict__ y) {
+  __shared__ Cx<R> tile[1 << kTileBits];
+  const int n = c.n;
+  const uint32_t cmask = (1u << n) - 1u;
+  const uint64_t base = (uint64_t)blockIdx.x << kTileBits;
+  const uint32_t tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < kTilePer; ++s) tile[tid + kTileThreads * s] = x[base + tid + kTileThreads * s];
+  __syncthreads();
+#pragma unroll 1
+  for (int s = 0; s < kTilePer; ++s) {
+    const uint32_t el = tid + kTileThreads * s;
+    const uint64_t idx = base + el;
+    const uint32_t r = (uint32_t)(idx >> n), col = (uint32_t)idx & cmask;
+    double dr = e[r], dc = e[col], loss = 0.0;
+    for (int p = 0; p < n; ++p) {
+      const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
+      dr -= rp ? c.delta[p] : 0.0;
+      dc -= cp ? c.delta[p] : 0.0;
+      loss += 0.5 * c.gamma_r * (double)(rp + cp) + ((rp ^ cp) ? c.gamma_phi : 0.0);
+    }
+    const Cx<R> v = tile[el];
+    double are = -loss * (double)v.x + (dr - dc) * (double)v.y;
+    double aim = -loss * (double)v.y - (dr - dc) * (double)v.x;
+    for (int p = 0; p < n; ++p) {
+      const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
+      const int qr = n + p;  // index bit of the row flip
+      const Cx<R> a = qr < kTileBits ? tile[el ^ (1u << qr)] : x[idx ^ (uint64_t(1) << qr)];
+      const double hr = rp ? c.up_re[p] : c.dn_re[p], hi = rp ? c.up_im[p] : c.dn_im[p];
+      are += hi * (double)a.x + hr * (double)a.y;
+      aim += hi * (double)a.y - hr * (double)a.x;
+      const Cx<R> b = p < kTileBits ? tile[el ^ (1u << p)] : x[idx ^ (uint64_t(1) << p)];
+      const double gr = cp ? c.dn_re[p] : c.up_re[p], gi = cp ? c.dn_im[p] : c.up_im[p];
+      are += -gi * (double)b.x - gr * (double)b.y;
+      aim += gr * (double)b.x - gi * (double)b.y;
+      if (c.gamma_r != 0.0 && !rp && !cp) {
+        const uint64_t src = idx | (uint64_t(1) << qr) | (uint64_t(1) << p);
+        const Cx<R> q = qr < kTileBits ? tile[(uint32_t)(src - base)] : x[src];
+        are += c.gamma_r * (double)q.x;
+        aim += c.gamma_r * (double)q.y;
+      }
+    }
+    Cx<R> o;
+    o.x = (R)are;
+    o.y = (R)aim;
+    y[idx] = o;
+  }
+}
+
 // Diagonal of rho: out[r] = Re rho_rr (FP64), r < 2^n.
 template <class R>
 __global__ __launch_bounds__(kBlock) void rho_diag_kernel(const Cx<R>* __restrict__ x, const int n,
@@ -87,6 +146,16 @@ __global__ __launch_bounds__(kBlock) void rho_diag_kernel(const Cx<R>* __restric
 hipError_t liouvillian_apply(int prec, const LindbladCoef& c, const double* e, const void* x,
                              void* y, hipStream_t s) {
   const uint64_t count = uint64_t(1) << (2 * c.n);
+  if (2 * c.n >= kTileBits) {
+    const uint32_t g = (uint32_t)(count >> kTileBits);
+    if (prec == kC128)
+      hipLaunchKernelGGL(liouvillian_tile_kernel<double>, dim3(g), dim3(kTileThreads), 0, s, c, e,
+                         (const double2*)x, (double2*)y);
+    else
+      hipLaunchKernelGGL(liouvillian_tile_kernel<float>, dim3(g), dim3(kTileThreads), 0, s, c, e,
+                         (const float2*)x, (float2*)y);
+    return hipGetLastError();
+  }
   uint64_t g = (count + kBlock - 1) / kBlock;
   if (g > 8192) g = 8192;
   if (prec == kC128)

@@ -74,6 +74,32 @@ def test_liouvillian_against_dense_superoperator(ctx, n, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("n", [6, 7, 9, 11])
+def test_tiled_liouvillian_against_matrix_form(ctx, n, prec):
+    """From 6 atoms the Liouvillian runs on LDS tiles of 4096 elements (low bits in LDS,
+    higher bits from neighbouring tiles): element by element against the oracle's
+    matrix-product form, with both channels on and a per-site drive with phases."""
+    import torch
+    rng = np.random.default_rng(40 + n)
+    xyz = wl.random_register(n, 18.0, 4.0, rng)
+    om, de, ph = pulses(n, 100, rng)
+    rates = (0.9, 0.35)
+    rho = random_rho(n, rng)
+    if prec == "c64":
+        rho = rho.astype(np.complex64).astype(np.complex128)
+    reg = rsv.rsv_register_create(ctx, xyz, wl.C6_RB, prec)
+    x = dev(rho, prec)
+    y = torch.empty_like(x)
+    rsv.rsv_lindblad_apply(reg, rsv.PulseArrays(om, de, ph), 4, 10, rates, x, y)
+    got = host(y, n)
+    rsv.rsv_register_destroy(reg)
+    u = model.interaction_matrix(xyz, wl.C6_RB)
+    h = model.dense_hamiltonian(u, *model.step_parameters(n, om, de, ph, 10, 4))
+    ref = lindblad.apply_liouvillian(rho, h, lindblad.jump_operators(n, *rates))
+    assert rel_err(got, ref) <= TOL[prec] * 10, n
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("n,per_site,rates", [(2, True, (0.7, 0.45)), (4, False, (1.5, 0.0)),
                                               (4, True, (0.0, 2.0)), (5, False, (0.3, 0.3))])
 def test_evolution_against_dense_oracle(ctx, n, per_site, rates, prec):

@@ -93,3 +93,17 @@ def test_library_dense_expm_against_scipy(m, scale):
     assert _dense_expm()(m, a.ctypes.data, out.ctypes.data) == 0
     ref = expm(a)
     assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * max(1.0, scale)
+
+
+def test_matrix_form_equals_superoperator():
+    """The matrix-product form of d rho/dt against the Kronecker-product superoperator."""
+    rng = np.random.default_rng(8)
+    n = 3
+    xyz = wl.random_register(n, 12.0, 4.0, rng)
+    u = model.interaction_matrix(xyz, wl.C6_RB)
+    h = model.dense_hamiltonian(u, rng.uniform(0, 9, n), rng.uniform(-5, 5, n), rng.uniform(-1, 1, n))
+    ops = lindblad.jump_operators(n, 0.8, 0.3)
+    a = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    rho = a @ a.conj().T
+    want = (lindblad.liouvillian(h, ops) @ rho.reshape(-1)).reshape(8, 8)
+    np.testing.assert_allclose(lindblad.apply_liouvillian(rho, h, ops), want, atol=1e-12)
