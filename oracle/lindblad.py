@@ -53,6 +53,29 @@ def apply_liouvillian(rho, h, ops) -> np.ndarray:
     return out
 
 
+def liouvillian_element(r: int, c: int, rho, u, omega, delta, phi, gamma_r: float,
+                        gamma_phi: float) -> complex:
+    """(d rho/dt)_rc from matrix elements, for large N: (H rho)_rc is row r of H applied to
+    column c of rho, (rho H)_rc = conj((H conj(rho_r.))_c) with rho_r. row r (H Hermitian),
+    and per atom i (level bits ri, ci of r and c) the relaxation adds gamma_r rho_{r+, c+}
+    (both levels raised to 1) when ri = ci = 0 and removes gamma_r (ri + ci)/2 rho_rc, the
+    dephasing removes gamma_phi rho_rc when ri != ci."""
+    n = len(omega)
+    rho = np.asarray(rho)
+    h_rho = model.hamiltonian_row(r, rho[:, c], u, omega, delta, phi)
+    rho_h = np.conj(model.hamiltonian_row(c, np.conj(rho[r, :]), u, omega, delta, phi))
+    out = -1j * (h_rho - rho_h)
+    lr, lc = model.atom_levels(r, n), model.atom_levels(c, n)
+    for i in range(n):
+        bit = 1 << (n - 1 - i)
+        if lr[i] == 0 and lc[i] == 0:
+            out += gamma_r * rho[r | bit, c | bit]
+        out -= 0.5 * gamma_r * (lr[i] + lc[i]) * rho[r, c]
+        if lr[i] != lc[i]:
+            out -= gamma_phi * rho[r, c]
+    return complex(out)
+
+
 def evolve(xyz, c6, omega, delta, phi, t_ns: int, dt_ns: int, rho0, gamma_r: float,
            gamma_phi: float, steps=None, first_step: int = 0) -> np.ndarray:
     """rho after steps first_step .. first_step + steps - 1 of rho_{k+1} = exp(dt L_k) rho_k."""

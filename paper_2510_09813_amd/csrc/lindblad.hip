@@ -16,26 +16,28 @@
 // where D_x = E_x - sum_p delta_p x_p is H's diagonal (E_x the interaction energy of pattern
 // x), h(1) = <1|h_p|0> = Omega_p/2 e^{-i phi_p} and h(0) = <0|h_p|1>.  Every element needs
 // 3n + 1 inputs; arithmetic is FP64, results are stored in the storage precision, and the
-// 4^n vector is at most 4 GiB (n <= 14).  Below 6 atoms one thread per element gathers its
-// inputs through the cache; from 6 atoms on, tiles of 4096 elements go through LDS.
+// 4^n vector is at most 4 GiB (n <= 14).  Up to 12 atoms one thread per element gathers its
+// inputs through the cache (the whole density matrix fits the 256 MB last-level cache); from
+// 13 atoms on, tiles of 4096 elements go through LDS.
 #include "device_common.h"
 #include "lindblad.h"
 
 namespace rsv {
 namespace {
 
-template <class R>
+template <class R, int N>
 __global__ __launch_bounds__(kBlock) void liouvillian_kernel(const LindbladCoef c,
                                                              const double* __restrict__ e,
                                                              const Cx<R>* __restrict__ x,
                                                              Cx<R>* __restrict__ y) {
-  const int n = c.n;
+  constexpr int n = N;
   const uint64_t count = uint64_t(1) << (2 * n);
   const uint32_t cmask = (1u << n) - 1u;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += stride) {
     const uint32_t r = (uint32_t)(idx >> n), col = (uint32_t)idx & cmask;
     double dr = e[r], dc = e[col], loss = 0.0;
+#pragma unroll
     for (int p = 0; p < n; ++p) {
       const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
       dr -= rp ? c.delta[p] : 0.0;
@@ -46,6 +48,7 @@ __global__ __launch_bounds__(kBlock) void liouvillian_kernel(const LindbladCoef 
     // (-i (dr - dc) - loss) * v
     double are = -loss * (double)v.x + (dr - dc) * (double)v.y;
     double aim = -loss * (double)v.y - (dr - dc) * (double)v.x;
+#pragma unroll
     for (int p = 0; p < n; ++p) {
       const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
       // row flip: -i h(r_p) rho_{r^p, c}
@@ -74,18 +77,21 @@ __global__ __launch_bounds__(kBlock) void liouvillian_kernel(const LindbladCoef 
   }
 }
 
-// The same operator on tiles of 2^12 consecutive elements (n >= 6): the tile sits in LDS, so
+// The same operator on tiles of 2^12 consecutive elements (n >= 13): the tile sits in LDS, so
 // the flips of the 12 low index bits (the column bits, and for n < 12 the low row bits) read
 // LDS; the flips of higher bits read the neighbouring tiles from global memory (one coalesced
 // read per bit), and the relaxation's double flips read LDS when both bits lie in the tile.
 constexpr int kTileBits = 12, kTileThreads = 512, kTilePer = (1 << kTileBits) / kTileThreads;
+// the tiled form from 13 atoms: at 12 atoms (a 256 MB density matrix, last-level-cache
+// resident) the gather form measured 0.58 ms against 0.85 ms, at 13 atoms 3.09 against 2.85
+constexpr int kLiouvillianTileAtoms = 13;
 
-template <class R>
+template <class R, int N>
 __global__ __launch_bounds__(kTileThreads) void liouvillian_tile_kernel(
     const LindbladCoef c, const double* __restrict__ e, const Cx<R>* __restrict__ x,
     Cx<R>* __restrict__ y) {
   __shared__ Cx<R> tile[1 << kTileBits];
-  const int n = c.n;
+  constexpr int n = N;
   const uint32_t cmask = (1u << n) - 1u;
   const uint64_t base = (uint64_t)blockIdx.x << kTileBits;
   const uint32_t tid = threadIdx.x;
@@ -98,6 +104,7 @@ __global__ __launch_bounds__(kTileThreads) void liouvillian_tile_kernel(
     const uint64_t idx = base + el;
     const uint32_t r = (uint32_t)(idx >> n), col = (uint32_t)idx & cmask;
     double dr = e[r], dc = e[col], loss = 0.0;
+#pragma unroll
     for (int p = 0; p < n; ++p) {
       const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
       dr -= rp ? c.delta[p] : 0.0;
@@ -107,6 +114,7 @@ __global__ __launch_bounds__(kTileThreads) void liouvillian_tile_kernel(
     const Cx<R> v = tile[el];
     double are = -loss * (double)v.x + (dr - dc) * (double)v.y;
     double aim = -loss * (double)v.y - (dr - dc) * (double)v.x;
+#pragma unroll
     for (int p = 0; p < n; ++p) {
       const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
       const int qr = n + p;  // index bit of the row flip
@@ -141,30 +149,50 @@ __global__ __launch_bounds__(kBlock) void rho_diag_kernel(const Cx<R>* __restric
     out[r] = (double)x[((uint64_t)r << n) | r].x;
 }
 
+template <class R, int N>
+void launch_liouvillian(const LindbladCoef& c, const double* e, const void* x, void* y,
+                        hipStream_t s) {
+  constexpr uint64_t count = uint64_t(1) << (2 * N);
+  if constexpr (N >= kLiouvillianTileAtoms) {
+    hipLaunchKernelGGL((liouvillian_tile_kernel<R, N>), dim3((uint32_t)(count >> kTileBits)),
+                       dim3(kTileThreads), 0, s, c, e, (const Cx<R>*)x, (Cx<R>*)y);
+  } else {
+    uint64_t g = (count + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL((liouvillian_kernel<R, N>), dim3((uint32_t)g), dim3(kBlock), 0, s, c, e,
+                       (const Cx<R>*)x, (Cx<R>*)y);
+  }
+}
+
+template <class R>
+hipError_t liouvillian_r(const LindbladCoef& c, const double* e, const void* x, void* y,
+                         hipStream_t s) {
+  switch (c.n) {
+    case 1: launch_liouvillian<R, 1>(c, e, x, y, s); break;
+    case 2: launch_liouvillian<R, 2>(c, e, x, y, s); break;
+    case 3: launch_liouvillian<R, 3>(c, e, x, y, s); break;
+    case 4: launch_liouvillian<R, 4>(c, e, x, y, s); break;
+    case 5: launch_liouvillian<R, 5>(c, e, x, y, s); break;
+    case 6: launch_liouvillian<R, 6>(c, e, x, y, s); break;
+    case 7: launch_liouvillian<R, 7>(c, e, x, y, s); break;
+    case 8: launch_liouvillian<R, 8>(c, e, x, y, s); break;
+    case 9: launch_liouvillian<R, 9>(c, e, x, y, s); break;
+    case 10: launch_liouvillian<R, 10>(c, e, x, y, s); break;
+    case 11: launch_liouvillian<R, 11>(c, e, x, y, s); break;
+    case 12: launch_liouvillian<R, 12>(c, e, x, y, s); break;
+    case 13: launch_liouvillian<R, 13>(c, e, x, y, s); break;
+    case 14: launch_liouvillian<R, 14>(c, e, x, y, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t liouvillian_apply(int prec, const LindbladCoef& c, const double* e, const void* x,
                              void* y, hipStream_t s) {
-  const uint64_t count = uint64_t(1) << (2 * c.n);
-  if (2 * c.n >= kTileBits) {
-    const uint32_t g = (uint32_t)(count >> kTileBits);
-    if (prec == kC128)
-      hipLaunchKernelGGL(liouvillian_tile_kernel<double>, dim3(g), dim3(kTileThreads), 0, s, c, e,
-                         (const double2*)x, (double2*)y);
-    else
-      hipLaunchKernelGGL(liouvillian_tile_kernel<float>, dim3(g), dim3(kTileThreads), 0, s, c, e,
-                         (const float2*)x, (float2*)y);
-    return hipGetLastError();
-  }
-  uint64_t g = (count + kBlock - 1) / kBlock;
-  if (g > 8192) g = 8192;
-  if (prec == kC128)
-    hipLaunchKernelGGL(liouvillian_kernel<double>, dim3((uint32_t)g), dim3(kBlock), 0, s, c, e,
-                       (const double2*)x, (double2*)y);
-  else
-    hipLaunchKernelGGL(liouvillian_kernel<float>, dim3((uint32_t)g), dim3(kBlock), 0, s, c, e,
-                       (const float2*)x, (float2*)y);
-  return hipGetLastError();
+  static_assert(kMaxLindbladAtoms == 14, "liouvillian_r instantiates 1..14 atoms");
+  return prec == kC128 ? liouvillian_r<double>(c, e, x, y, s) : liouvillian_r<float>(c, e, x, y, s);
 }
 
 hipError_t rho_diagonal(int prec, int n, const void* x, double* out, hipStream_t s) {

@@ -74,11 +74,11 @@ def test_liouvillian_against_dense_superoperator(ctx, n, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("n", [6, 7, 9, 11])
-def test_tiled_liouvillian_against_matrix_form(ctx, n, prec):
-    """From 6 atoms the Liouvillian runs on LDS tiles of 4096 elements (low bits in LDS,
-    higher bits from neighbouring tiles): element by element against the oracle's
-    matrix-product form, with both channels on and a per-site drive with phases."""
+@pytest.mark.parametrize("n", [6, 7, 9, 12])
+def test_liouvillian_against_matrix_form(ctx, n, prec):
+    """6..12 atoms (the gather form up to the largest size it serves): element by element
+    against the oracle's matrix-product form, with both channels on and a per-site drive
+    with phases."""
     import torch
     rng = np.random.default_rng(40 + n)
     xyz = wl.random_register(n, 18.0, 4.0, rng)
@@ -97,6 +97,38 @@ def test_tiled_liouvillian_against_matrix_form(ctx, n, prec):
     h = model.dense_hamiltonian(u, *model.step_parameters(n, om, de, ph, 10, 4))
     ref = lindblad.apply_liouvillian(rho, h, lindblad.jump_operators(n, *rates))
     assert rel_err(got, ref) <= TOL[prec] * 10, n
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_tiled_liouvillian_sampled_at_13_atoms(ctx, prec):
+    """13 atoms: the Liouvillian on LDS tiles of 4096 elements (column bits in LDS, row bits
+    from neighbouring tiles), 400 sampled elements (tile corners, diagonal and random)
+    against the oracle's element-by-element form; any matrix will do, L is linear."""
+    import torch
+    n = 13
+    rng = np.random.default_rng(130)
+    xyz = wl.random_register(n, 20.0, 4.0, rng)
+    om, de, ph = pulses(n, 100, rng)
+    rates = (0.9, 0.35)
+    g = torch.Generator(device="cuda:0").manual_seed(13)
+    x = torch.randn(1 << (2 * n), dtype=getattr(torch, DT[prec]), device="cuda:0", generator=g)
+    y = torch.empty_like(x)
+    reg = rsv.rsv_register_create(ctx, xyz, wl.C6_RB, prec)
+    rsv.rsv_lindblad_apply(reg, rsv.PulseArrays(om, de, ph), 4, 10, rates, x, y)
+    torch.cuda.synchronize()
+    rsv.rsv_register_destroy(reg)
+    rho = x.cpu().numpy().astype(np.complex128).reshape(1 << n, 1 << n)
+    out = y.cpu().numpy().astype(np.complex128).reshape(1 << n, 1 << n)
+    d = 1 << n
+    pts = [(0, 0), (d - 1, d - 1), (0, d - 1), (d - 1, 0), (1, 4095), (4096 // d, 4095 % d)]
+    pts += [(int(i), int(i)) for i in rng.integers(0, d, 30)]
+    pts += [(int(a), int(b)) for a, b in rng.integers(0, d, (364, 2))]
+    u = model.interaction_matrix(xyz, wl.C6_RB)
+    pars = model.step_parameters(n, om, de, ph, 10, 4)
+    for r, c in pts:
+        want = lindblad.liouvillian_element(r, c, rho, u, *pars, *rates)
+        scale = np.abs(rho[r, :]).max() + np.abs(rho[:, c]).max()
+        assert abs(out[r, c] - want) <= TOL[prec] * 1e3 * scale, (r, c, out[r, c], want)
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
