@@ -219,8 +219,9 @@ typedef struct {
 int rsv_lindblad_apply(rsv_register* reg, const rsv_pulses* pulses, int64_t step, int dt_ns,
                        const rsv_lindblad* rates, const void* d_in, void* d_out, void* hip_stream);
 /* rho <- exp(dt L_{k}) rho for the requested steps (opts as for rsv_evolve_device; reorth is
- * ignored, kmax <= 63), each exponential by the Arnoldi process (two passes of classical
- * Gram-Schmidt, FP64 inner products, host FP64 exponential of the Hessenberg matrix) to the
+ * ignored, kmax <= 63), each exponential by the Arnoldi process (classical Gram-Schmidt with
+ * a second pass when the first removes most of the new vector, FP64 inner products, host
+ * FP64 exponential of the Hessenberg matrix) to the
  * estimate |rho| h_{m+1,m} |[exp(dt H_m) e_1]_m| <= tol, halving the step without
  * convergence.  stats->norm_final is the Frobenius norm of the final rho. */
 int rsv_lindblad_evolve_device(rsv_register* reg, const rsv_pulses* pulses,

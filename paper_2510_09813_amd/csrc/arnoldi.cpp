@@ -28,16 +28,19 @@ int norm2(ArnoldiSpace& sp, const void* x, hipStream_t s, double* out) {
 }
 
 // <u_i, y> for i < k (Re, Im interleaved into dots[2 i], dots[2 i + 1]).
-int dots_against(ArnoldiSpace& sp, int k, const void* y, hipStream_t s, double* dots) {
+// <u_i, y> for i < k, and <y, y> after them when self_dot (in the same sweeps over y).
+int dots_against(ArnoldiSpace& sp, int k, const void* y, hipStream_t s, double* dots,
+                 bool self_dot = false) {
   const int64_t nw = vec_num_partials(sp.prec, sp.nb);
-  for (int i0 = 0; i0 < k; i0 += kDotGroup) {
+  const int total = k + (self_dot ? 1 : 0);
+  for (int i0 = 0; i0 < total; i0 += kDotGroup) {
     DotGroup d{};
-    d.g = std::min(kDotGroup, k - i0);
-    for (int g = 0; g < d.g; ++g) d.x[g] = sp.vec[i0 + g];
+    d.g = std::min(kDotGroup, total - i0);
+    for (int g = 0; g < d.g; ++g) d.x[g] = i0 + g < k ? sp.vec[i0 + g] : y;
     HIP_TRY(multi_dot(sp.prec, sp.nb, d, y, sp.partial, s));
     HIP_TRY(finalize_rows(sp.partial, nw, 2 * d.g, sp.dscal + 2 * i0, s));
   }
-  return fetch(sp, 2 * k, s, dots);
+  return fetch(sp, 2 * total, s, dots);
 }
 
 int expm_once(const OpFn& op, ArnoldiSpace& sp, void* d_x, double tau, double tol, hipStream_t s,
@@ -64,12 +67,16 @@ int expm_once(const OpFn& op, ArnoldiSpace& sp, void* d_x, double tau, double to
   for (int j = 0; j < kmax; ++j) {
     RSV_TRY(op(v[j], w, s));  // w = Op u_j, v_j = s_j u_j
     st->krylov_iters += 1;
-    // y = Op v_j = s_j w, orthogonalised against v_0..v_j twice; the first pass applies s_j,
-    // so every stored vector has the size of a Hessenberg entry (no growth by |Op|^j, which
-    // would overflow complex64 storage)
+    // y = Op v_j = s_j w, orthogonalised against v_0..v_j by classical Gram-Schmidt; the first
+    // pass applies s_j, so every stored vector has the size of a Hessenberg entry (no growth
+    // by |Op|^j, which would overflow complex64 storage).  A second pass runs only when the
+    // first removed most of y: |y'| < |y| / sqrt(2) (the criterion of Daniel, Gragg, Kaufman
+    // and Stewart, 1976), the case where rounding in y' is no longer small against y'.
+    double y2 = 0.0, beta2 = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       const double f = pass == 0 ? scale[j] : 1.0;
-      RSV_TRY(dots_against(sp, j + 1, w, s, dots.data()));
+      RSV_TRY(dots_against(sp, j + 1, w, s, dots.data(), pass == 0));
+      if (pass == 0) y2 = f * f * dots[2 * (j + 1)];
       CombineCoef cc;
       std::memset(&cc, 0, sizeof cc);
       cc.m = j + 2;
@@ -87,12 +94,16 @@ int expm_once(const OpFn& op, ArnoldiSpace& sp, void* d_x, double tau, double to
       }
       HIP_TRY(krylov_combine(sp.prec, sp.nb, cc, t, sp.partial, s));
       std::swap(w, t);
+      HIP_TRY(finalize_sum(sp.partial, vec_num_partials(sp.prec, sp.nb), sp.dscal, s));
+      RSV_TRY(fetch(sp, 1, s, &beta2));
+      if (!std::isfinite(beta2)) return fail(RSV_ENUMERIC, "Arnoldi residual not finite");
+      if (pass == 0 && beta2 >= 0.5 * y2) break;
     }
-    HIP_TRY(finalize_sum(sp.partial, vec_num_partials(sp.prec, sp.nb), sp.dscal, s));
-    double b2 = 0.0;
-    RSV_TRY(fetch(sp, 1, s, &b2));
-    if (!std::isfinite(b2)) return fail(RSV_ENUMERIC, "Arnoldi residual not finite");
-    const double beta = std::sqrt(std::max(b2, 0.0));
+    // the scratch slots keep naming the two buffers that are not basis vectors, whichever
+    // way the passes swapped them (the next call takes its scratch from these slots)
+    v[kmax + 1] = w;
+    v[kmax + 2] = t;
+    const double beta = std::sqrt(std::max(beta2, 0.0));
     H(j + 1, j) = beta;  // h_{j+1,j} = |y - sum_i v_i <v_i, y>|
     m = j + 1;
     hm.assign((size_t)m * m, 0.0);
@@ -122,8 +133,8 @@ int expm_once(const OpFn& op, ArnoldiSpace& sp, void* d_x, double tau, double to
       return RSV_OK;
     }
     scale[j + 1] = 1.0 / beta;
-    std::swap(v[j + 1], w);  // the orthogonalised residual becomes u_{j+1}
-    v[kmax + 1] = w;
+    std::swap(v[j + 1], v[kmax + 1]);  // the orthogonalised residual becomes u_{j+1}
+    w = v[kmax + 1];
   }
   *converged = false;
   return RSV_OK;

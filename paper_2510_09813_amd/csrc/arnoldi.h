@@ -32,8 +32,9 @@ void arnoldi_carve(void* block, double* h_scal, int prec, int nb, int kmax, Arno
 
 using OpFn = std::function<int(const void* in, void* out, hipStream_t s)>;
 
-// x <- exp(tau Op) x with the Arnoldi process (two passes of classical Gram-Schmidt per new
-// vector, FP64 inner products), y = exp(tau H_m) e_1 from the Hessenberg matrix, converged when
+// x <- exp(tau Op) x with the Arnoldi process (classical Gram-Schmidt, a second pass when the
+// first removes most of the new vector, FP64 inner products), y = exp(tau H_m) e_1 from the
+// Hessenberg matrix, converged when
 // |x| h_{m+1,m} |y_m| <= tol (the estimate of Saad 1992 used by the Lanczos path), x = |x| V_m y.
 // Without convergence in kmax vectors the step is split in halves (exact for a constant
 // operator), at most max_depth levels deep, else RSV_ENOTCONV.
