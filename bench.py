@@ -609,6 +609,10 @@ def main():
                      # the state in and out only: E_b is formed on chip from small tables
                      "compulsory_bytes_per_amplitude": 32,
                      "achieved_compulsory": round(gbs128 * 32 / 40, 1),
+                     "frac_compulsory": round(gbs128 * 32 / 40 / PEAK_HBM_GBS, 4),
+                     # two passes move >= 80 B/amplitude: frac <= 0.5 at peak, 0.39 at the
+                     # best measured copy (6.2 TB/s); the 0.70 target needs one pass
+                     "frac_target": 0.70, "frac_ceiling_two_pass": 0.5,
                      "traffic": pmc_traffic("c128")},
         "register_build_ms": round(evolve_timed.register_ms, 3),
         "occupations_sum": round(float(occ.sum()), 6), "n_shots": len(shots),

@@ -71,6 +71,28 @@ def test_members_match_oracle(ctx, prec, n, members, pack):
     assert observables.fidelity_loss(got[100]["state"], got[101]["state"]) > 1e-8
 
 
+def test_per_site_members_with_phase(ctx):
+    """A job with per-site pulses and a phase: members keep their per-site rows, scaled and
+    offset atom by atom, against the oracle with the same draws."""
+    n, members = 7, 5
+    rng = np.random.default_rng(77)
+    w = job(n, "c128", 200, seed=7)
+    om = np.outer(rng.uniform(0.5, 1.5, n), w.omega)
+    de = np.outer(rng.uniform(0.5, 1.5, n), w.delta)
+    ph = np.outer(rng.uniform(-1, 1, n), np.linspace(0, 1, w.t_ns + 1))
+
+    def f(srv):
+        rsv.rsv_server_submit_ensemble(srv, w.xyz, w.c6, rsv.PulseArrays(om, de, ph),
+                                       rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12), NOISE, 3,
+                                       members, "c128", return_state=True, tag=100)
+    got = run(ctx, f, members, 12)
+    for s in range(members):
+        fac, off, pos = noise.member(3, s, n, *NOISE, w.xyz)
+        mom, mde = noise.member_pulses(om, de, fac, off)
+        ref = evolve.evolve(pos, w.c6, mom, mde, ph, w.t_ns, w.dt_ns, method="dense")
+        assert observables.fidelity_loss(ref, got[100 + s]["state"]) <= INFID["c128"], s
+
+
 @pytest.mark.parametrize("prec,pack", [("c64", 13), ("c128", 0)])
 def test_member_alone_equals_in_ensemble(ctx, prec, pack):
     n, members, s = 9, 8, 5
