@@ -232,6 +232,78 @@ constexpr int lo_min_waves() {
   return sizeof(R) == 8 && LB == 12 && NT == 512 && CM != kCoefSite ? 4 : 1;
 }
 
+// Which tile positions a thread holds.  The extended low pass issues about ten vector
+// memory instructions per amplitude (its tile, t, the diagonal table, the extension's
+// neighbours, the store).  With 8-byte complex64 accesses the vector memory unit's address
+// stage was busy 86 % of the pass (TA_BUSY) while the bytes ran below the copy ceiling, so
+// there a thread holds pairs of adjacent amplitudes and every access moves 16 bytes per lane:
+// the register bits below VB are the lowest tile bits, then come the thread bits, then the
+// other register bits.  At 27 atoms this took the complex64 low pass from 0.91 to 0.76 ms.
+// (VB = 0 for complex128, whose amplitude is already 16 bytes, and for the unextended
+// complex64 tiles, where the pairs would cost registers the wide tiles do not have.)
+template <class R, int A, int E>
+constexpr int lo_vec_bits() { return sizeof(R) == 4 && A >= 2 && E > 0 ? 1 : 0; }
+
+// Tile position of register slot s of thread tid.
+template <int TB, int VB>
+__device__ __forceinline__ uint32_t lo_pos(uint32_t tid, int s) {
+  // (sums rather than ors: tid < 2^TB, and the compiler then folds the slot part into the
+  // immediate offsets of the accesses)
+  return (tid << VB) + (uint32_t)(s & ((1 << VB) - 1)) + ((uint32_t)(s >> VB) << (TB + VB));
+}
+
+// Tile-position bit of register bit q.
+template <int TB, int VB>
+constexpr int lo_reg_bit(int q) { return q < VB ? q : q + TB; }
+
+typedef float lo_f4 __attribute__((ext_vector_type(4)));
+typedef float lo_f2 __attribute__((ext_vector_type(2)));
+
+// r[0 .. 2^VB) = the 2^VB adjacent amplitudes at p (aligned to 2^VB amplitudes); nt: a
+// non-temporal load.
+template <class R, int VB>
+__device__ __forceinline__ void ld_run(const Cx<R>* p, Cx<R>* r, bool nt = false) {
+  if constexpr (VB == 0) {
+    if (nt) {
+      r[0].x = __builtin_nontemporal_load(&p->x);
+      r[0].y = __builtin_nontemporal_load(&p->y);
+    } else {
+      r[0] = *p;
+    }
+  } else {
+    static_assert(sizeof(R) == 4 && VB == 1, "pairs of complex64 amplitudes only");
+    if (nt) {
+      // (two 8-byte non-temporal loads, which the compiler joins into one 16-byte access;
+      // a non-temporal load of the 16-byte vector type loses the hint)
+      const double* q = reinterpret_cast<const double*>(p);
+      const lo_f2 a = __builtin_bit_cast(lo_f2, __builtin_nontemporal_load(q));
+      const lo_f2 b = __builtin_bit_cast(lo_f2, __builtin_nontemporal_load(q + 1));
+      r[0] = Cx<R>{a.x, a.y};
+      r[1] = Cx<R>{b.x, b.y};
+    } else {
+      const lo_f4 w = *reinterpret_cast<const lo_f4*>(p);
+      r[0] = Cx<R>{w.x, w.y};
+      r[1] = Cx<R>{w.z, w.w};
+    }
+  }
+}
+
+// The 2^VB adjacent amplitudes at p (aligned) = r[0 .. 2^VB).
+template <class R, int VB>
+__device__ __forceinline__ void st_run(Cx<R>* p, const Cx<R>* r, int streaming) {
+  if constexpr (VB == 0) {
+    put(p, r[0], streaming);
+  } else {
+    lo_f4* q = reinterpret_cast<lo_f4*>(p);
+    const lo_f4 w = {r[0].x, r[0].y, r[1].x, r[1].y};
+    if (streaming) {
+      __builtin_nontemporal_store(w, q);
+    } else {
+      *q = w;
+    }
+  }
+}
+
 // E > 0: the pass also flips the E amplitude bits LB + g0 .. LB + g0 + E - 1 (g0 =
 // p.ext_bit; the planner puts them at the top), whose neighbours lie in E other tiles of the
 // same group of 2^E tiles (those differing in tile-index bits g0 .. g0 + E - 1).  Those are
@@ -245,7 +317,9 @@ __global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_l
   static_assert(LB >= TB, "tile smaller than the workgroup");
   constexpr int A = 1 << (LB - TB);  // amplitudes per thread
   constexpr int RB = LB - TB;        // bits held in registers
-  __shared__ C tile[1 << LB];
+  constexpr int VB = lo_vec_bits<R, A, E>();
+  constexpr int V = 1 << VB;         // adjacent amplitudes per access
+  __shared__ __align__(16) C tile[1 << LB];
   __shared__ R lut[CM == kCoefSite ? 1024 : 1];
   __shared__ double red[NT / 64];
 
@@ -269,25 +343,21 @@ __global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_l
   double eth = et[0];  // the tile's high-bit pairs plus the couplings of the thread bits
 #pragma unroll
   for (int q = 0; q < TB; ++q)
-    if ((tid >> q) & 1u) eth += et[1 + q];
+    if ((tid >> q) & 1u) eth += et[1 + VB + q];
   // (the input test sits outside the loops, so that the loads of a stored input are issued
   // back to back rather than one branch at a time)
   if (!p.x1 && !p.x2 && co.a0 == 1.0) {
 #pragma unroll
-    for (int s = 0; s < A; ++s) v[s] = p.x0[base + tid + NT * s];
+    for (int s = 0; s < A; s += V) ld_run<R, VB>(&p.x0[base + lo_pos<TB, VB>(tid, s)], &v[s]);
   } else {
 #pragma unroll
-    for (int s = 0; s < A; ++s) v[s] = form<R>(p, co, base + tid + NT * s);
+    for (int s = 0; s < A; ++s) v[s] = form<R>(p, co, base + lo_pos<TB, VB>(tid, s));
   }
   if (p.tb) {
     // the high-pass partial is read once: a non-temporal load keeps it from displacing the
     // state tiles that neighbouring workgroups read through the cache
 #pragma unroll
-    for (int s = 0; s < A; ++s) {
-      const C* q = &p.tb[base + tid + NT * s];
-      tv[s].x = __builtin_nontemporal_load(&q->x);
-      tv[s].y = __builtin_nontemporal_load(&q->y);
-    }
+    for (int s = 0; s < A; s += V) ld_run<R, VB>(&p.tb[base + lo_pos<TB, VB>(tid, s)], &tv[s], true);
   } else {
 #pragma unroll
     for (int s = 0; s < A; ++s) tv[s] = C{0, 0};
@@ -297,17 +367,16 @@ __global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_l
     double es = eth;
 #pragma unroll
     for (int q = 0; q < RB; ++q)
-      if ((s >> q) & 1) es += et[1 + TB + q];
-    dg[s] = (R)(p.elo[tid + NT * s] + es);
+      if ((s >> q) & 1) es += et[1 + lo_reg_bit<TB, VB>(q)];
+    dg[s] = (R)(p.elo[lo_pos<TB, VB>(tid, s)] + es);
   }
 #pragma unroll
-  for (int s = 0; s < A; ++s) tile[tid + NT * s] = v[s];
+  for (int s = 0; s < A; ++s) tile[lo_pos<TB, VB>(tid, s)] = v[s];
   if (p.u_out) {
 #pragma unroll
-    for (int s = 0; s < A; ++s) {
-      put(&p.u_out[base + tid + NT * s], v[s], p.streaming);
-      nrm = norm_add(nrm, (double)v[s].x, (double)v[s].y);
-    }
+    for (int s = 0; s < A; s += V) st_run<R, VB>(&p.u_out[base + lo_pos<TB, VB>(tid, s)], &v[s], p.streaming);
+#pragma unroll
+    for (int s = 0; s < A; ++s) nrm = norm_add(nrm, (double)v[s].x, (double)v[s].y);
   }
   // flips of the bits above the tile: bit LB + tb of every amplitude here is bit tb of the
   // tile index, so its coefficient is the same for the whole workgroup; the terms join the
@@ -325,7 +394,7 @@ __global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_l
     const uint32_t nbase = (blk ^ (1u << tb)) << LB;
     C nb[A];
 #pragma unroll
-    for (int s = 0; s < A; ++s) nb[s] = p.x0[nbase + tid + NT * s];
+    for (int s = 0; s < A; s += V) ld_run<R, VB>(&p.x0[nbase + lo_pos<TB, VB>(tid, s)], &nb[s]);
 #pragma unroll
     for (int s = 0; s < A; ++s) {
       tv[s].x += cr * nb[s].x - ci * nb[s].y;
@@ -337,7 +406,7 @@ __global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_l
     // the thread's own amplitudes come back from the tile: not holding them in registers
     // across the barrier leaves room for the neighbour loads to be in flight together
 #pragma unroll
-    for (int s = 0; s < A; ++s) v[s] = tile[tid + NT * s];
+    for (int s = 0; s < A; ++s) v[s] = tile[lo_pos<TB, VB>(tid, s)];
   }
 
   double dot = 0.0;
@@ -347,17 +416,17 @@ __global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_l
     C acc[A];
 #pragma unroll
     for (int s = 0; s < A; ++s) {
-      const R d = dg[s] + detuning<R, CM>(c, lut, base + tid + NT * s);
+      const R d = dg[s] + detuning<R, CM>(c, lut, base + lo_pos<TB, VB>(tid, s));
       acc[s] = C{d * v[s].x, d * v[s].y};
     }
 #pragma unroll
     for (int q = 0; q < TB; ++q) {
       const bool bit = (tid >> q) & 1u;
-      const R cr = (R)(bit ? c.up_re[q] : c.dn_re[q]);
-      const R ci = (R)(bit ? c.up_im[q] : c.dn_im[q]);
+      const R cr = (R)(bit ? c.up_re[VB + q] : c.dn_re[VB + q]);
+      const R ci = (R)(bit ? c.up_im[VB + q] : c.dn_im[VB + q]);
 #pragma unroll
       for (int s = 0; s < A; ++s) {
-        const C nb = tile[(tid + NT * s) ^ (1u << q)];
+        const C nb = tile[lo_pos<TB, VB>(tid, s) ^ (1u << (VB + q))];
         acc[s].x += cr * nb.x - ci * nb.y;
         acc[s].y += cr * nb.y + ci * nb.x;
       }
@@ -365,27 +434,34 @@ __global__ __launch_bounds__(NT, (lo_min_waves<R, LB, NT, CM, E>())) void hpsi_l
 #pragma unroll
     for (int s = 0; s < A; ++s) {
 #pragma unroll
-      for (int q = 0; q < RB; ++q) cmad<R>(acc[s], c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
+      for (int q = 0; q < RB; ++q)
+        cmad<R>(acc[s], c, lo_reg_bit<TB, VB>(q), (s >> q) & 1, v[s ^ (1 << q)]);
       if (E > 0 || p.tb) cadd<R>(acc[s], tv[s]);
-      put(&p.out[base + tid + NT * s], acc[s], p.streaming);
       dot += (double)v[s].x * (double)acc[s].x + (double)v[s].y * (double)acc[s].y;
     }
+#pragma unroll
+    for (int s = 0; s < A; s += V) st_run<R, VB>(&p.out[base + lo_pos<TB, VB>(tid, s)], &acc[s], p.streaming);
   } else {
 #pragma unroll
-    for (int s = 0; s < A; ++s) {
-      const uint32_t e = tid + NT * s;
-      const uint32_t b = base + e;
-      const R d = dg[s] + detuning<R, CM>(c, lut, b);
-      C acc = {d * v[s].x, d * v[s].y};
-      DriveSum<R, CM> ds;
+    for (int s0 = 0; s0 < A; s0 += V) {
+      C acc[V];
 #pragma unroll
-      for (int q = 0; q < TB; ++q) ds.add(c, q, (tid >> q) & 1, tile[e ^ (1u << q)]);
+      for (int k = 0; k < V; ++k) {
+        const int s = s0 + k;
+        const uint32_t e = lo_pos<TB, VB>(tid, s);
+        const R d = dg[s] + detuning<R, CM>(c, lut, base + e);
+        acc[k] = C{d * v[s].x, d * v[s].y};
+        DriveSum<R, CM> ds;
 #pragma unroll
-      for (int q = 0; q < RB; ++q) ds.add(c, TB + q, (s >> q) & 1, v[s ^ (1 << q)]);
-      ds.finish(c, acc);
-      if (E > 0 || p.tb) cadd<R>(acc, tv[s]);
-      put(&p.out[b], acc, p.streaming);
-      dot += (double)v[s].x * (double)acc.x + (double)v[s].y * (double)acc.y;
+        for (int q = 0; q < TB; ++q) ds.add(c, VB + q, (tid >> q) & 1, tile[e ^ (1u << (VB + q))]);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) ds.add(c, lo_reg_bit<TB, VB>(q), (s >> q) & 1, v[s ^ (1 << q)]);
+        ds.finish(c, acc[k]);
+        if (E > 0 || p.tb) cadd<R>(acc[k], tv[s]);
+        if constexpr (V == 1) put(&p.out[base + e], acc[0], p.streaming);
+        dot += (double)v[s].x * (double)acc[k].x + (double)v[s].y * (double)acc[k].y;
+      }
+      if constexpr (V > 1) st_run<R, VB>(&p.out[base + lo_pos<TB, VB>(tid, s0)], acc, p.streaming);
     }
   }
   if (p.part_norm) {
