@@ -492,6 +492,59 @@ def capacity_leg(rsv, wl, ctx, steps):
     return out
 
 
+def observables_leg(rsv, ctx, w, reg, psi, first_step, steps=10, reps=5):
+    """Observables of the 27-atom complex128 state: <n_i n_j> (one pass over the state, HIP
+    events), <H_k> (one H|psi> and a dot), and the cost of recording <n_i> after every step
+    inside the final combination (steps first_step.. on a copy of the state, with and without
+    the recording)."""
+    import torch
+    n = w.n_atoms
+    pulses = rsv.PulseArrays(w.omega, w.delta)
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    corr_ms = timed(lambda: rsv.rsv_correlations_device(ctx, n, psi, "c128"))
+    corr = rsv.rsv_correlations_device(ctx, n, psi, "c128")
+    occ = rsv.rsv_occupations_device(ctx, n, psi, "c128")
+    energy_ms = timed(lambda: rsv.rsv_energy_device(reg, pulses, first_step, w.dt_ns, psi))
+    energy = rsv.rsv_energy_device(reg, pulses, first_step, w.dt_ns, psi)
+    log(f"observables: <n_i n_j> {corr_ms:.3f} ms, <H> {energy_ms:.3f} ms")
+    copy = psi.clone()
+    opts = rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12, first_step, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_plain = rsv.rsv_evolve_device(reg, pulses, opts, copy)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    copy.copy_(psi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_obs, rec = rsv.rsv_evolve_device_observed(reg, pulses, opts, copy, 1)
+    torch.cuda.synchronize()
+    observed = time.perf_counter() - t0
+    log(f"observables: {steps} steps {plain:.3f} s plain, {observed:.3f} s recording <n_i> every step")
+    del copy
+    return {"workload": f"random27-sweep state after step {first_step - 1}, complex128",
+            "correlations_ms": round(corr_ms, 4),
+            "correlations_gbps": round(16.0 * (1 << n) / (corr_ms * 1e-3) / 1e9, 1),
+            "correlations_diag_vs_occupations": float(np.abs(np.diag(corr) - occ).max()),
+            "energy_ms": round(energy_ms, 4), "energy": energy,
+            "observed_steps": steps, "plain_ms_per_step": round(plain / steps * 1e3, 3),
+            "observed_ms_per_step": round(observed / steps * 1e3, 3),
+            "krylov_iters": [int(st_plain.krylov_iters), int(st_obs.krylov_iters)],
+            "recorded_occupations_last_sum": round(float(rec[-1].sum()), 6)}
+
+
 def cpu_baseline(wl, gpu_iters_per_step):
     """The CPU oracle as it stands, on the host: one complete time step of its Krylov
     propagator (diagonal tensor, Lanczos with full re-orthogonalisation, tol 1e-13,
@@ -551,7 +604,7 @@ def main():
     ap.add_argument("--n30-steps", type=int, default=3,
                     help="steps of the 30-atom complex64 leg (0: skip it)")
     ap.add_argument("--no-next", dest="next_rows", action="store_false",
-                    help="skip the Lindblad and gradient legs")
+                    help="skip the observables, Lindblad and gradient legs")
     ap.add_argument("--serve-full", type=int, default=0,
                     help="only serve this many jobs of the stream at --serve-rate and report")
     ap.add_argument("--serve-rate", type=float, default=2.4)
@@ -618,7 +671,6 @@ def main():
         "occupations_sum": round(float(occ.sum()), 6), "n_shots": len(shots),
         "device_copy_gbps": round(cp_gbs, 1),
     }
-    rsv.rsv_register_destroy(reg128)
 
     if not args.no_c64:
         reg64, psi64, st64, wall64 = evolve_timed(rsv, ctx, w, "c64", W, K)
@@ -640,6 +692,9 @@ def main():
         }
         rsv.rsv_register_destroy(reg64)
         del psi64
+    if args.next_rows:
+        out["observables"] = observables_leg(rsv, ctx, w, reg128, psi128, min(W + K, w.n_steps - 10))
+    rsv.rsv_register_destroy(reg128)
     del psi128
     torch.cuda.empty_cache()
     if args.n30_steps > 0:

@@ -77,65 +77,129 @@ __global__ __launch_bounds__(kBlock) void liouvillian_kernel(const LindbladCoef 
   }
 }
 
-// The same operator on tiles of 2^12 consecutive elements (n >= 13): the tile sits in LDS, so
-// the flips of the 12 low index bits (the column bits, and for n < 12 the low row bits) read
-// LDS; the flips of higher bits read the neighbouring tiles from global memory (one coalesced
-// read per bit), and the relaxation's double flips read LDS when both bits lie in the tile.
-constexpr int kTileBits = 12, kTileThreads = 512, kTilePer = (1 << kTileBits) / kTileThreads;
-// the tiled form from 13 atoms: at 12 atoms (a 256 MB density matrix, last-level-cache
-// resident) the gather form measured 0.58 ms against 0.85 ms, at 13 atoms 3.09 against 2.85
+// The same operator on tiles of 2^12 consecutive elements (n >= 13), one tile per
+// workgroup.  The tile holds whole column ranges: its columns' flips (index bits 0..11) read
+// LDS.  Every index bit above the tile (all row bits, and from 13 atoms the top column bits)
+// has one value across the tile, so its flip reads the neighbouring tile in one coalesced
+// sweep with one coefficient for the workgroup; as in the H|psi> low pass, the loads of one
+// neighbour tile are issued together before any is used, and all of them before the
+// barrier.  A relaxation source rho_{r|p, c|p} lies in the tile of the flipped row bit, at
+// the element with column bit p set; it is read from global memory as well (that tile was
+// just swept: mostly cache hits), and only where the tile's row bit p is 0.
+constexpr int kTileBits = 12, kTileThreads = 1024, kTilePer = (1 << kTileBits) / kTileThreads;
+constexpr int kTileThreadBits = 10;
+static_assert((1 << kTileThreadBits) == kTileThreads, "thread bits");
+// The tiled form from 13 atoms; below, one thread per element gathers its inputs through
+// the cache.  At 12 atoms (a 256 MB density matrix, last-level-cache resident) the gather
+// form measured 0.58 ms against 0.61 ms tiled (complex128; complex64 0.45 against 0.44).  At
+// 13 atoms this form takes 2.86 ms (complex128) and 1.92 ms (complex64), where a tile kernel
+// that read each neighbour where it was used took 2.84 and 2.35 ms: complex128 is bound by
+// neighbour tiles that miss the caches (14 index bits lie above the tile).
 constexpr int kLiouvillianTileAtoms = 13;
 
 template <class R, int N>
 __global__ __launch_bounds__(kTileThreads) void liouvillian_tile_kernel(
     const LindbladCoef c, const double* __restrict__ e, const Cx<R>* __restrict__ x,
     Cx<R>* __restrict__ y) {
-  __shared__ Cx<R> tile[1 << kTileBits];
+  using C = Cx<R>;
+  static_assert(N >= kTileBits, "tiles hold whole column ranges (12 atoms and more)");
   constexpr int n = N;
-  const uint32_t cmask = (1u << n) - 1u;
-  const uint64_t base = (uint64_t)blockIdx.x << kTileBits;
+  __shared__ C tile[1 << kTileBits];
   const uint32_t tid = threadIdx.x;
+  const uint64_t base = (uint64_t)xcd_remap(blockIdx.x, gridDim.x) << kTileBits;
+  double are[kTilePer], aim[kTilePer];
 #pragma unroll
-  for (int s = 0; s < kTilePer; ++s) tile[tid + kTileThreads * s] = x[base + tid + kTileThreads * s];
+  for (int s = 0; s < kTilePer; ++s) {
+    tile[tid + kTileThreads * s] = x[base + tid + kTileThreads * s];
+    are[s] = 0.0;
+    aim[s] = 0.0;
+  }
+  // flips of the index bits above the tile
+#pragma unroll
+  for (int q = kTileBits; q < 2 * n; ++q) {
+    const bool bit = (base >> q) & 1u;
+    const uint64_t nbase = base ^ (uint64_t(1) << q);
+    C nb[kTilePer];
+#pragma unroll
+    for (int s = 0; s < kTilePer; ++s) nb[s] = x[nbase + tid + kTileThreads * s];
+    if (q >= n) {
+      // row flip of bit p: -i h(r_p) rho_{r^p, c} = (hi a.x + hr a.y) + i (hi a.y - hr a.x)
+      const int p = q - n;
+      const double hr = bit ? c.up_re[p] : c.dn_re[p], hi = bit ? c.up_im[p] : c.dn_im[p];
+#pragma unroll
+      for (int s = 0; s < kTilePer; ++s) {
+        are[s] += hi * (double)nb[s].x + hr * (double)nb[s].y;
+        aim[s] += hi * (double)nb[s].y - hr * (double)nb[s].x;
+      }
+    } else {
+      // column flip of bit q: +i h(1 - c_q) rho_{r, c^q} = (-gi b.x - gr b.y) + i (gr b.x - gi b.y)
+      const double gr = bit ? c.dn_re[q] : c.up_re[q], gi = bit ? c.dn_im[q] : c.up_im[q];
+#pragma unroll
+      for (int s = 0; s < kTilePer; ++s) {
+        are[s] += -gi * (double)nb[s].x - gr * (double)nb[s].y;
+        aim[s] += gr * (double)nb[s].x - gi * (double)nb[s].y;
+      }
+    }
+  }
+  // relaxation feeds (0, 0) of atom p from (1, 1): rho_{r|p, c|p} where r_p = c_p = 0
+  if (c.gamma_r != 0.0) {
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      if ((base >> (n + p)) & 1u) continue;  // r_p = 1 across the tile
+      if (p >= kTileBits && ((base >> p) & 1u)) continue;  // c_p = 1 across the tile
+      // element el (with c_p = 0) takes its source at element el | 2^p of the tile with row
+      // bit p set (every address formed here lies inside the matrix, also where c_p = 1)
+      const uint64_t sbase = (base | (uint64_t(1) << (n + p))) | (p >= kTileBits ? (uint64_t(1) << p) : 0);
+      const uint32_t pin = p < kTileBits ? (1u << p) : 0u;
+      C src[kTilePer];
+#pragma unroll
+      for (int s = 0; s < kTilePer; ++s) {
+        const uint32_t el = tid + kTileThreads * s;
+        const bool on = !(el & pin);
+        src[s] = on ? x[sbase + (el | pin)] : C{0, 0};
+      }
+#pragma unroll
+      for (int s = 0; s < kTilePer; ++s) {
+        are[s] += c.gamma_r * (double)src[s].x;
+        aim[s] += c.gamma_r * (double)src[s].y;
+      }
+    }
+  }
   __syncthreads();
-#pragma unroll 1
+
+  const uint32_t cmask = (1u << n) - 1u;
+  const uint32_t r = (uint32_t)(base >> n);  // one row per tile
+  double dr = e[r];
+#pragma unroll
+  for (int p = 0; p < n; ++p)
+    if ((r >> p) & 1u) dr -= c.delta[p];
+#pragma unroll
   for (int s = 0; s < kTilePer; ++s) {
     const uint32_t el = tid + kTileThreads * s;
     const uint64_t idx = base + el;
-    const uint32_t r = (uint32_t)(idx >> n), col = (uint32_t)idx & cmask;
-    double dr = e[r], dc = e[col], loss = 0.0;
+    const uint32_t col = (uint32_t)idx & cmask;
+    double dc = e[col], loss = 0.0;
 #pragma unroll
     for (int p = 0; p < n; ++p) {
       const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
-      dr -= rp ? c.delta[p] : 0.0;
       dc -= cp ? c.delta[p] : 0.0;
       loss += 0.5 * c.gamma_r * (double)(rp + cp) + ((rp ^ cp) ? c.gamma_phi : 0.0);
     }
-    const Cx<R> v = tile[el];
-    double are = -loss * (double)v.x + (dr - dc) * (double)v.y;
-    double aim = -loss * (double)v.y - (dr - dc) * (double)v.x;
+    const C v = tile[el];
+    // (-i (dr - dc) - loss) v
+    double ore = -loss * (double)v.x + (dr - dc) * (double)v.y + are[s];
+    double oim = -loss * (double)v.y - (dr - dc) * (double)v.x + aim[s];
 #pragma unroll
-    for (int p = 0; p < n; ++p) {
-      const uint32_t rp = (r >> p) & 1u, cp = (col >> p) & 1u;
-      const int qr = n + p;  // index bit of the row flip
-      const Cx<R> a = qr < kTileBits ? tile[el ^ (1u << qr)] : x[idx ^ (uint64_t(1) << qr)];
-      const double hr = rp ? c.up_re[p] : c.dn_re[p], hi = rp ? c.up_im[p] : c.dn_im[p];
-      are += hi * (double)a.x + hr * (double)a.y;
-      aim += hi * (double)a.y - hr * (double)a.x;
-      const Cx<R> b = p < kTileBits ? tile[el ^ (1u << p)] : x[idx ^ (uint64_t(1) << p)];
+    for (int p = 0; p < kTileBits; ++p) {
+      const uint32_t cp = (el >> p) & 1u;
+      const C b = tile[el ^ (1u << p)];
       const double gr = cp ? c.dn_re[p] : c.up_re[p], gi = cp ? c.dn_im[p] : c.up_im[p];
-      are += -gi * (double)b.x - gr * (double)b.y;
-      aim += gr * (double)b.x - gi * (double)b.y;
-      if (c.gamma_r != 0.0 && !rp && !cp) {
-        const uint64_t src = idx | (uint64_t(1) << qr) | (uint64_t(1) << p);
-        const Cx<R> q = qr < kTileBits ? tile[(uint32_t)(src - base)] : x[src];
-        are += c.gamma_r * (double)q.x;
-        aim += c.gamma_r * (double)q.y;
-      }
+      ore += -gi * (double)b.x - gr * (double)b.y;
+      oim += gr * (double)b.x - gi * (double)b.y;
     }
-    Cx<R> o;
-    o.x = (R)are;
-    o.y = (R)aim;
+    C o;
+    o.x = (R)ore;
+    o.y = (R)oim;
     y[idx] = o;
   }
 }
