@@ -676,8 +676,9 @@ int enqueue(rsv_server* srv, std::vector<std::unique_ptr<Job>>& jobs, uint64_t* 
       srv->queue.push_back(jobs[i].release());
     }
   }
-  if (jobs.size() == 1) srv->cv_work.notify_one();
-  else srv->cv_work.notify_all();
+  // every idle lane looks: one woken lane may not be able to take the job (the small-job
+  // lane takes packed jobs only, and a job may not fit the arena beside another lane's)
+  srv->cv_work.notify_all();
   return RSV_OK;
 }
 

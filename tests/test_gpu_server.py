@@ -313,3 +313,20 @@ def test_per_result_precision_report(ctx):
         assert 0.0 <= c["infidelity_fp64"] <= 1e-6
         assert abs(c["infidelity_fp64"] - loss) <= 1e-13, (c["infidelity_fp64"], loss)
         assert abs(c["max_occ_err_fp64"] - np.abs(occ - c["occupations"]).max()) <= 1e-12
+
+
+def test_plain_job_after_idle_wakes_a_regular_lane(ctx):
+    """With packing on, one lane takes packed batches only.  A plain job submitted while every
+    lane waits must wake a lane that can run it: each of these jobs arrives at an idle server
+    and has to finish without any later submission or completion to wake the lanes again."""
+    jobs = [w for w in small_stream(40, seed=91) if w.n_atoms >= 14][:6]
+    assert len(jobs) == 6
+    srv = rsv.rsv_server_create(ctx, n_lanes=1, arena_bytes=512 << 20, pack_max_atoms=12)
+    try:
+        for k, w in enumerate(jobs):
+            time.sleep(0.3)  # both lanes are waiting for work
+            jid = submit(srv, w, "c64", tag=k, shots=0, state=False)
+            got = drain(srv, 1, timeout_s=30)
+            assert got[0]["job_id"] == jid and got[0]["status"] == rsv.RSV_OK, got[0]["error"]
+    finally:
+        rsv.rsv_server_destroy(srv)
