@@ -100,13 +100,14 @@ def test_liouvillian_against_matrix_form(ctx, n, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_tiled_liouvillian_sampled_at_13_atoms(ctx, prec):
-    """13 atoms: the Liouvillian on LDS tiles of 4096 elements (column bits in LDS, row bits
-    from neighbouring tiles), 400 sampled elements (tile corners, diagonal and random)
-    against the oracle's element-by-element form; any matrix will do, L is linear."""
+@pytest.mark.parametrize("n", [13, 14])
+def test_tiled_liouvillian_sampled(ctx, n, prec):
+    """13 and 14 atoms (the largest density matrix, 4 GiB in complex128): the Liouvillian on
+    LDS tiles of 4096 elements (column bits in LDS, row bits and the top column bits from
+    neighbouring tiles), 400 sampled elements (tile corners, diagonal and random) against
+    the oracle's element-by-element form; any matrix will do, L is linear."""
     import torch
-    n = 13
-    rng = np.random.default_rng(130)
+    rng = np.random.default_rng(117 + n)
     xyz = wl.random_register(n, 20.0, 4.0, rng)
     om, de, ph = pulses(n, 100, rng)
     rates = (0.9, 0.35)
