@@ -21,7 +21,7 @@
 //    up to H - r high bits, flips those high bits.  The
 //    first high pass writes t, later ones accumulate into it.  The passes are as few as the
 //    shortest run allows; the tile bits left over lengthen the runs, the forming pass's
-//    first.  For vectors far beyond the caches the passes store with streaming stores.
+//    first.  For vectors of 64 MiB and more the passes request streaming stores.
 //
 // The first pass of a sweep may *form* its input from up to three stored vectors,
 //   u = a0 x0 + (a1 + c * dot[0]) x1 + a2 x2,
@@ -105,11 +105,13 @@ struct PassArgs {
   double* part_dot;  // optional: per-workgroup Re<u, out>
   int ext_bit;       // low pass: tile-index bit of the first extension bit
   uint32_t nblk;
-  int streaming;     // vectors far larger than the caches: stores bypass them
+  int streaming;     // vectors larger than the caches hold: stores bypass them
 };
 
 // Store of one amplitude; streaming stores skip the caches (nothing written by a pass is
-// read again before the whole vector has streamed through).
+// read again before the whole vector has streamed through).  Where both branches store the
+// same value to the same address, the compiler may merge them into one plain store and drop
+// the hint: the high pass's partial t keeps it, the low pass's stores do not.
 template <class T>
 __device__ __forceinline__ void put(T* p, const T& v, int streaming) {
   if (streaming) {
@@ -649,8 +651,10 @@ hipError_t sweep_t(int n, const StepCoef& c, const double* dtab, const SweepIn& 
   base.elo = dtab;
   base.etile = dtab + (size_t(1) << lbits);
   base.out = (Cx<R>*)out;
-  // vectors of 256 MiB and more (the size of the last-level cache) stream past the caches
-  base.streaming = (size_t(1) << n) * sizeof(Cx<R>) >= (size_t(256) << 20);
+  // vectors of 64 MiB and more stream past the caches: a Lanczos iteration touches five of
+  // them, more than the 256 MB last-level cache holds (from 64 MiB rather than 256 MiB the
+  // step measured 1.5-2.5 % faster at 22-24 atoms)
+  base.streaming = (size_t(1) << n) * sizeof(Cx<R>) >= (size_t(64) << 20);
 
   const bool first = part != kLaterPasses, later = part != kFirstPass;
   if (n < 8) {
