@@ -463,7 +463,8 @@ def gradient_leg(rsv, wl, ctx, n, steps):
 
 def capacity_leg(rsv, wl, ctx, steps):
     """The 5x6 triangular quench at 30 atoms in complex64 (FP64 Lanczos scalars and host
-    tridiagonal exponential, kmax 20, dt = 5 ns): the first `steps` steps from |0...0>."""
+    tridiagonal exponential, kmax 20, dt = 5 ns) from |0...0>: step 0 acquires the 192 GiB
+    workspace (timed apart), steps 1..steps are timed."""
     import torch
     w = wl.triangular30()
     ws = rsv.rsv_workspace_bytes(w.n_atoms, w.kmax, "c64")
@@ -473,19 +474,25 @@ def capacity_leg(rsv, wl, ctx, steps):
     pulses = rsv.PulseArrays(w.omega, w.delta)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12, 0, steps), psi)
+    rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12, 0, 1), psi)
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st = rsv.rsv_evolve_device(reg, pulses, rsv.evolve_opts(w.dt_ns, w.tol, w.kmax, 12, 1, steps), psi)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     occ = rsv.rsv_occupations_device(ctx, w.n_atoms, psi, "c64")
     out = {"workload": "triangular30-quench", "n_atoms": w.n_atoms, "precision": "complex64",
-           "steps": steps, "ms_per_step": round(wall / steps * 1e3, 2),
+           "steps": steps, "timed_steps": f"1..{steps}", "ms_per_step": round(wall / steps * 1e3, 2),
+           "first_step_with_workspace_s": round(first, 3),
            "sim_us_per_s": round(steps * w.dt_ns * 1e-3 / wall, 5),
            "krylov_iters_per_step": round(st.krylov_iters / steps, 2),
            "krylov_max": int(st.krylov_max), "norm_final": st.norm_final,
            "workspace_bytes": int(ws), "workspace_gib": round(ws / 2**30, 2),
            "device_bytes_in_use": int(rsv.rsv_ctx_bytes_in_use(ctx)),
            "occupations_sum": round(float(occ.sum()), 6)}
-    log(f"N=30 c64: {steps} steps in {wall:.2f} s, workspace {ws / 2**30:.1f} GiB")
+    log(f"N=30 c64: step 0 with the workspace {first:.2f} s; {steps} steps in {wall:.2f} s, "
+        f"workspace {ws / 2**30:.1f} GiB")
     rsv.rsv_register_destroy(reg)
     del psi
     torch.cuda.empty_cache()
