@@ -41,8 +41,12 @@ def test_correlations_of_device_states(ctx, n, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("n,per_site", [(3, False), (6, True), (11, False), (16, True), (21, False)])
+@pytest.mark.parametrize("n,per_site", [(3, False), (6, True), (11, False), (16, True), (21, False),
+                                        (22, False), (23, True)])
 def test_energy_of_device_states(ctx, n, per_site, prec):
+    """<H_k> of a random state through the H|psi> passes, against the oracle's H applied
+    to it; at 22 (complex64) and 23 atoms the low pass also flips top bits from
+    neighbouring tiles."""
     rng = np.random.default_rng(200 + n)
     xyz = wl.random_register(n, 25.0, 4.5, rng)
     om = rng.uniform(0, 15, (n, 41) if per_site else 41)
