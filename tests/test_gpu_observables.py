@@ -24,9 +24,10 @@ def ctx():
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("n", [1, 2, 5, 9, 12, 13, 17])
+@pytest.mark.parametrize("n", [1, 2, 5, 9, 12, 13, 17, 22])
 def test_correlations_of_device_states(ctx, n, prec):
-    """Tile boundaries at 12 bits, ragged chunks below, zero blocks."""
+    """Tile boundaries at 12 bits, ragged chunks below, zero blocks; at 22 atoms ten index
+    bits above the 4096-amplitude chunks."""
     rng = np.random.default_rng(100 + n)
     psi = wl.random_state(n, rng) * (rng.uniform(0, 1, 1 << n) ** 2)
     psi[rng.integers(0, 1 << n, max(1, (1 << n) // 8))] = 0
