@@ -13,9 +13,9 @@
 //    high-bit pairs and the low-high couplings), so no 2^n diagonal is read from HBM, plus
 //    the detuning from the bit pattern; and it adds the high-pass result t.  Where that
 //    saves a high pass, it also flips up to 7 of the top bits, reading those neighbours from
-//    the other tiles of a group in global memory (mostly cache hits): n = 22..29 complex128
+//    the other tiles of a group in global memory (mostly cache hits): n = 23..29 complex128
 //    and 22..29 complex64 then need one high pass, over the bits between (complex64 on
-//    12-bit tiles up to n = 28).
+//    12-bit tiles of 256 threads holding pairs of adjacent amplitudes, up to n = 28).
 //  * high passes (n > L): a tile of 2^H amplitudes (H = 13 for complex128, 12 for
 //    complex64), 2^r contiguous (r = 3..6: runs of 64 B to 1 KiB) times the combinations of
 //    up to H - r high bits, flips those high bits.  The
